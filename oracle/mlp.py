@@ -1,0 +1,105 @@
+"""FP64 oracle of the learned cross-rank predictor (an addition to the paper).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The paper computes every cross rank by binary search (Section 2, Steps 1-2).
+The library can instead predict a rank with a small network and correct the
+prediction with the bounded exponential search of ``oracle.gallop``; the
+network never changes a result, only where the search starts.  This module
+is the plain numpy definition of that network, its loss, its gradient and
+its optimiser step, against which the GPU kernels are checked.
+
+Model: a 2-layer perceptron 1 -> 32 (ReLU) -> 1 mapping a key to its
+normalised rank r / len(X) in the target array X, i.e. a model of the
+cumulative distribution of X.
+
+Parameter vector (97 values): W1[0:32], b1[32:64], w2[64:96], b2[96].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+HIDDEN = 32
+NPARAM = 3 * HIDDEN + 1
+
+
+def unsigned_order(keys: np.ndarray) -> np.ndarray:
+    """Map keys to unsigned integers with the same order (int32: flip the sign bit)."""
+    if keys.dtype == np.int32:
+        return (keys.view(np.uint32) ^ np.uint32(0x80000000)).astype(np.uint64)
+    return keys.astype(np.uint64)
+
+
+def key_bits(keys: np.ndarray) -> int:
+    return 64 if keys.dtype == np.uint64 else 32
+
+
+def features(keys: np.ndarray) -> np.ndarray:
+    """phi(key) = log2(u + 1) / bits, u the order-preserving unsigned form."""
+    u = unsigned_order(keys).astype(np.float64)
+    return np.log2(u + 1.0) / key_bits(keys)
+
+
+def unpack(params: np.ndarray):
+    p = np.asarray(params, dtype=np.float64)
+    return p[0:32], p[32:64], p[64:96], p[96]
+
+
+def forward(params, phi):
+    """Returns (y, pre, h): output, hidden pre-activation and activation."""
+    W1, b1, w2, b2 = unpack(params)
+    pre = np.outer(phi, W1) + b1
+    h = np.maximum(pre, 0.0)
+    y = h @ w2 + b2
+    return y, pre, h
+
+
+def loss(params, phi, target):
+    """Mean squared error of the normalised rank."""
+    y, _, _ = forward(params, phi)
+    d = y - target
+    return float(np.mean(d * d))
+
+
+def loss_and_grad(params, phi, target):
+    """Loss and its gradient by the chain rule (ReLU derivative 0 at pre = 0)."""
+    W1, b1, w2, b2 = unpack(params)
+    y, pre, h = forward(params, phi)
+    S = len(phi)
+    d = y - target
+    dy = 2.0 * d / S
+    g = np.empty(NPARAM)
+    g[64:96] = h.T @ dy
+    g[96] = dy.sum()
+    dh = np.outer(dy, w2) * (pre > 0.0)
+    g[0:32] = dh.T @ phi
+    g[32:64] = dh.sum(axis=0)
+    return float(np.mean(d * d)), g
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, 2015) with bias correction; step >= 1.
+    Returns new (params, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def init_params(sample_phi_sorted: np.ndarray) -> np.ndarray:
+    """Knot initialisation: unit 32 hinges ReLU(phi - c_k) with c_k the
+    (k + 0.5)/32 quantile of the (sorted) training features, zero output
+    weights and bias."""
+    S = len(sample_phi_sorted)
+    p = np.zeros(NPARAM)
+    idx = ((np.arange(HIDDEN) + 0.5) * S / HIDDEN).astype(np.int64)
+    p[0:32] = 1.0
+    p[32:64] = -sample_phi_sorted[np.minimum(idx, S - 1)] if S else 0.0
+    return p
+
+
+def predict_rank(params, keys: np.ndarray, length: int) -> np.ndarray:
+    """Predicted rank clamp(round(y * length), 0, length)."""
+    y, _, _ = forward(params, features(keys))
+    return np.clip(np.rint(y * length), 0, length).astype(np.int64)

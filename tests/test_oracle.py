@@ -1,0 +1,433 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix.
+
+Nothing here compares the oracle with itself.  The pins are:
+  * Figure 1 of the paper (block starts, cross ranks, the ten subproblems and
+    their case letters), stored in tests/golden/figure1.json;
+  * the counting definitions of rank_low / rank_high (Section 2);
+  * brute force: Python's sort of (key, source, index)-tagged elements, and
+    numpy's stable argsort of the concatenation A || B;
+  * the closed-form output positions (Section 2, after Observation 1);
+  * invariants: the 2p subproblems tile A, B and C, each holds at most
+    ceil(n/p_a) + ceil(m/p_b) elements (Section 2, Theorem 1 discussion),
+    Observation 1;
+  * special cases (empty inputs, all-equal keys, disjoint ranges, p >= n+m).
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "figure1.json")
+DTYPES = [np.int32, np.uint32, np.uint64]
+
+
+def fig1():
+    with open(GOLD) as f:
+        g = json.load(f)
+    return g, np.array(g["A"], dtype=np.int32), np.array(g["B"], dtype=np.int32)
+
+
+def brute_merge(A, B, pa=None, pb=None):
+    """Stable merge by sorting (key, source, index) tags with Python's sort."""
+    tags = [(int(a), 0, i) for i, a in enumerate(A)] + [(int(b), 1, j) for j, b in enumerate(B)]
+    tags.sort()
+    keys = np.array([t[0] for t in tags], dtype=A.dtype) if tags else np.zeros(0, A.dtype)
+    if pa is None:
+        return keys, None
+    pay = np.array([(pa if s == 0 else pb)[i] for _, s, i in tags], dtype=np.uint32)
+    return keys, pay
+
+
+def argsort_merge(A, B, pa, pb):
+    """numpy stable argsort of A || B: equal keys keep A first, then index order."""
+    cat = np.concatenate([A, B])
+    order = np.argsort(cat, kind="stable")
+    return cat[order], np.concatenate([pa, pb])[order]
+
+
+def rand_sorted(g, n, alphabet, dtype):
+    if dtype == np.int32:
+        x = g.integers(-alphabet // 2, alphabet - alphabet // 2, size=n).astype(np.int32)
+    elif dtype == np.uint32:
+        x = (g.integers(0, alphabet, size=n) + (2 ** 32 - alphabet) * g.integers(0, 2)).astype(np.uint32)
+    else:
+        x = (g.integers(0, alphabet, size=n).astype(np.uint64) * np.uint64(0x0100000000000001))
+    x.sort()
+    return x
+
+
+# --------------------------------------------------------------------------
+# Figure 1 (Section 2): the worked example, n = 18, m = 15, p = 5
+# --------------------------------------------------------------------------
+
+def test_figure1_block_starts():
+    g, A, B = fig1()
+    p = g["p"]
+    assert [oracle.block_start(len(A), p, i) for i in range(p + 1)] == g["x"]
+    assert [oracle.block_start(len(B), p, j) for j in range(p + 1)] == g["y"]
+
+
+def test_figure1_cross_ranks():
+    g, A, B = fig1()
+    xbar, ybar = oracle.cross_ranks(A, B, g["p"])
+    assert xbar.tolist() == g["xbar"]
+    assert ybar.tolist() == g["ybar"]
+
+
+def test_figure1_subproblems_and_cases():
+    g, A, B = fig1()
+    p = g["p"]
+    xbar, ybar = oracle.cross_ranks(A, B, p)
+    pcs = oracle.pieces(len(A), len(B), p, p, xbar, ybar)
+    got = {}
+    for s, (alo, ahi, blo, bhi, coff, kase) in enumerate(pcs):
+        name = ("A%d" % s) if s < p else ("B%d" % (s - p))
+        got[name] = dict(A=[alo, ahi - 1] if ahi > alo else None,
+                         B=[blo, bhi - 1] if bhi > blo else None,
+                         C=[coff, coff + (ahi - alo) + (bhi - blo) - 1], case=chr(kase))
+    for ref in g["subproblems_caption"]:
+        mine = got[ref["block"]]
+        assert mine["A"] == ref["A"], ref
+        assert mine["B"] == ref["B"], ref
+        assert mine["C"] == ref["C"], ref
+    for i, letter in g["a_side_cases"].items():
+        assert got["A" + i]["case"] == letter
+    for j, letter in g["b_side_cases_named_in_caption"].items():
+        assert got["B" + j]["case"] == letter.upper()
+
+
+def test_figure1_merge():
+    g, A, B = fig1()
+    pa, pb = np.arange(len(A), dtype=np.uint32), np.arange(100, 100 + len(B), dtype=np.uint32)
+    ref_k, ref_p = brute_merge(A, B, pa, pb)
+    for f in (lambda: oracle.merge(A, B, pa, pb),
+              lambda: oracle.merge_by_pieces(A, B, g["p"], g["p"], pa, pb)):
+        c, pc = f()
+        assert c.tolist() == ref_k.tolist()
+        assert pc.tolist() == ref_p.tolist()
+
+
+# --------------------------------------------------------------------------
+# Ranks: counting definitions (Section 2, low and high rank)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_rank_counting_definition(dtype):
+    g = np.random.default_rng(7)
+    for _ in range(300):
+        n = int(g.integers(0, 30))
+        X = rand_sorted(g, n, int(g.integers(1, 12)), dtype)
+        probe = rand_sorted(g, 5, 14, dtype)
+        for x in probe:
+            lo, hi = oracle.rank_low(x, X), oracle.rank_high(x, X)
+            assert lo == int(np.sum(X < x))
+            assert hi == int(np.sum(X <= x))
+            # the defining inequalities with sentinels X[-1] = -inf, X[n] = +inf
+            assert (lo == 0 or X[lo - 1] < x) and (lo == n or x <= X[lo])
+            assert (hi == 0 or X[hi - 1] <= x) and (hi == n or x < X[hi])
+
+
+# --------------------------------------------------------------------------
+# O1 / O2 against brute force
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_merge_brute_force(dtype):
+    g = np.random.default_rng(11)
+    for _ in range(400):
+        n, m = int(g.integers(0, 41)), int(g.integers(0, 41))
+        alpha = int(g.integers(1, 51))
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        pa = g.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+        pb = g.integers(0, 2 ** 32, size=m, dtype=np.uint64).astype(np.uint32)
+        rk, rp = brute_merge(A, B, pa, pb)
+        c, pc = oracle.merge(A, B, pa, pb)
+        assert np.array_equal(c, rk) and np.array_equal(pc, rp)
+        c2, pc2, ok = oracle.merge_scatter(A, B, pa, pb)
+        assert ok
+        assert np.array_equal(c2, rk) and np.array_equal(pc2, rp)
+        ak, ap = argsort_merge(A, B, pa, pb)
+        assert np.array_equal(ak, rk) and np.array_equal(ap, rp)
+
+
+def test_merge_keys_only():
+    g = np.random.default_rng(3)
+    A, B = rand_sorted(g, 100, 20, np.uint32), rand_sorted(g, 70, 20, np.uint32)
+    c, pc = oracle.merge(A, B)
+    assert pc is None
+    assert np.array_equal(c, brute_merge(A, B)[0])
+
+
+# --------------------------------------------------------------------------
+# Steps 1-4: the method against brute force, exhaustively on tiny inputs
+# --------------------------------------------------------------------------
+
+def nondecreasing(length, alphabet):
+    return [np.array(c, dtype=np.int32)
+            for c in itertools.combinations_with_replacement(range(alphabet), length)]
+
+
+def check_tiling(n, m, p_a, p_b, pcs):
+    """The 2p subproblems tile A, B and C exactly once, and each holds at most
+    ceil(n/p_a) + ceil(m/p_b) elements."""
+    ca, cb, cc = np.zeros(n, int), np.zeros(m, int), np.zeros(n + m, int)
+    bound = -(-n // p_a) + -(-m // p_b)
+    for alo, ahi, blo, bhi, coff, _ in pcs:
+        assert 0 <= alo <= ahi <= n and 0 <= blo <= bhi <= m
+        ca[alo:ahi] += 1
+        cb[blo:bhi] += 1
+        cc[coff:coff + (ahi - alo) + (bhi - blo)] += 1
+        assert (ahi - alo) + (bhi - blo) <= bound
+    assert (ca == 1).all() and (cb == 1).all() and (cc == 1).all()
+
+
+def test_method_exhaustive_tiny():
+    seqs = [s for L in range(0, 5) for s in nondecreasing(L, 3)]
+    hit = set()
+    for A in seqs:
+        for B in seqs:
+            ref = brute_merge(A, B)[0]
+            n, m = len(A), len(B)
+            pa_src = np.arange(n, dtype=np.uint32)
+            pb_src = np.arange(n, n + m, dtype=np.uint32)
+            ref_p = brute_merge(A, B, pa_src, pb_src)[1]
+            for p_a in range(1, 7):
+                for p_b in range(1, 7):
+                    c, pc = oracle.merge_by_pieces(A, B, p_a, p_b, pa_src, pb_src)
+                    assert np.array_equal(c, ref) and np.array_equal(pc, ref_p), (A, B, p_a, p_b)
+                    xbar, ybar = oracle.cross_ranks(A, B, p_a, p_b)
+                    pcs = oracle.pieces(n, m, p_a, p_b, xbar, ybar)
+                    two = oracle.pieces(n, m, p_a, p_b, xbar, ybar, two_select=True)
+                    assert np.array_equal(pcs[:, :5], two[:, :5]), (A, B, p_a, p_b)
+                    check_tiling(n, m, p_a, p_b, pcs)
+                    hit.update(chr(k) for k in pcs[:, 5])
+    assert hit == set("abcdeABCDE"), hit
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_method_random(dtype):
+    g = np.random.default_rng(5)
+    hit = set()
+    for _ in range(1500):
+        n, m = int(g.integers(0, 65)), int(g.integers(0, 65))
+        alpha = int(g.integers(1, 65))
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        p_a, p_b = int(g.integers(1, 13)), int(g.integers(1, 13))
+        pa = np.arange(n, dtype=np.uint32)
+        pb = np.arange(n, n + m, dtype=np.uint32)
+        rk, rp = brute_merge(A, B, pa, pb)
+        c, pc = oracle.merge_by_pieces(A, B, p_a, p_b, pa, pb)
+        assert np.array_equal(c, rk) and np.array_equal(pc, rp)
+        xbar, ybar = oracle.cross_ranks(A, B, p_a, p_b)
+        pcs = oracle.pieces(n, m, p_a, p_b, xbar, ybar)
+        check_tiling(n, m, p_a, p_b, pcs)
+        two = oracle.pieces(n, m, p_a, p_b, xbar, ybar, two_select=True)
+        assert np.array_equal(pcs[:, :5], two[:, :5])
+        hit.update(chr(k) for k in pcs[:, 5])
+    assert hit == set("abcdeABCDE")
+
+
+def test_observation1():
+    """Cross ranks do not cross (Section 2, Observation 1): with a = A[i] and
+    j = rank_low(a, B), every B[j'] with j' < j has rank_high(B[j'], A) <= i,
+    and every B[j''] with j'' >= j has rank_high(B[j''], A) > i."""
+    g = np.random.default_rng(9)
+    for _ in range(300):
+        n, m = int(g.integers(1, 30)), int(g.integers(1, 30))
+        alpha = int(g.integers(1, 10))
+        A, B = rand_sorted(g, n, alpha, np.int32), rand_sorted(g, m, alpha, np.int32)
+        for i in range(n):
+            j = oracle.rank_low(A[i], B)
+            for jj in range(m):
+                r = oracle.rank_high(B[jj], A)
+                assert (r <= i) if jj < j else (r > i)
+
+
+def test_cross_ranks_monotone_large():
+    g = np.random.default_rng(1)
+    A = np.sort(g.integers(0, 65536, size=100_000).astype(np.int32))
+    B = np.sort(g.integers(0, 65536, size=60_000).astype(np.int32))
+    xbar, ybar = oracle.cross_ranks(A, B, 256)
+    assert (np.diff(xbar) >= 0).all() and (np.diff(ybar) >= 0).all()
+    xs = np.array([oracle.block_start(len(A), 256, i) for i in range(256)])
+    assert np.array_equal(xbar[:-1], np.searchsorted(B, A[xs], side="left"))
+    ys = np.array([oracle.block_start(len(B), 256, j) for j in range(256)])
+    assert np.array_equal(ybar[:-1], np.searchsorted(A, B[ys], side="right"))
+
+
+# --------------------------------------------------------------------------
+# Blocks (Section 2): sizes and membership against the definition
+# --------------------------------------------------------------------------
+
+def test_block_math():
+    for L in range(0, 45):
+        for p in range(1, 14):
+            starts = [oracle.block_start(L, p, i) for i in range(p + 1)]
+            sizes = np.diff(starts)
+            assert starts[0] == 0 and starts[-1] == L
+            c, r = -(-L // p), L % p
+            assert (sizes[:r] == c).all() and (sizes[r:] == L // p).all()
+            for k in range(L):
+                owners = [i for i in range(p) if starts[i] <= k < starts[i + 1]]
+                assert oracle.block_of(L, p, k) == owners[0]
+            assert oracle.block_of(L, p, L) == p
+
+
+# --------------------------------------------------------------------------
+# Special cases
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 2, 5, 64])
+def test_special_cases(p):
+    def both(A, B):
+        pa = np.arange(len(A), dtype=np.uint32)
+        pb = np.arange(len(A), len(A) + len(B), dtype=np.uint32)
+        c1, p1 = oracle.merge(A, B, pa, pb)
+        c2, p2 = oracle.merge_by_pieces(A, B, p, p, pa, pb)
+        assert np.array_equal(c1, c2) and np.array_equal(p1, p2)
+        return c1, p1
+    u = np.uint32
+    A = np.arange(10, dtype=u)
+    e = np.zeros(0, dtype=u)
+    assert np.array_equal(both(A, e)[0], A)                       # m = 0
+    assert np.array_equal(both(e, A)[0], A)                       # n = 0
+    eq = np.full(7, 5, dtype=u)
+    c, pc = both(eq, np.full(4, 5, dtype=u))                      # all equal: A || B
+    assert pc.tolist() == list(range(11))
+    c, pc = both(np.arange(5, dtype=u), np.arange(4, 9, dtype=u))  # max A == min B
+    assert pc.tolist() == list(range(10))
+    c, pc = both(np.arange(10, 15, dtype=u), np.arange(5, dtype=u))  # max B < min A: B || A
+    assert pc.tolist() == list(range(5, 10)) + list(range(5))
+    c, pc = both(np.array([3], u), np.array([3], u))
+    assert pc.tolist() == [0, 1]
+    c, pc = both(np.arange(0, 20, 2, dtype=u), np.arange(1, 21, 2, dtype=u))  # interleaved
+    assert c.tolist() == list(range(20))
+    assert pc.tolist() == [k // 2 + (k % 2) * 10 for k in range(20)]
+
+
+def test_many_blocks_small_subproblems():
+    """p >= n + m: every subproblem holds at most 2 elements."""
+    g = np.random.default_rng(2)
+    A, B = rand_sorted(g, 9, 4, np.int32), rand_sorted(g, 7, 4, np.int32)
+    xbar, ybar = oracle.cross_ranks(A, B, 20, 20)
+    pcs = oracle.pieces(9, 7, 20, 20, xbar, ybar)
+    assert ((pcs[:, 1] - pcs[:, 0]) + (pcs[:, 3] - pcs[:, 2]) <= 2).all()
+    check_tiling(9, 7, 20, 20, pcs)
+
+
+# --------------------------------------------------------------------------
+# O4: stable merge sort (Section 3)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,run_len", [(0, 4), (1, 4), (17, 1), (1000, 3), (5000, 512), (4096, 512),
+                                       (4097, 512), (3 * 512 + 5, 512)])
+def test_sort_against_stable_argsort(N, run_len):
+    g = np.random.default_rng(N + run_len)
+    keys = g.integers(0, max(1, N // 8), size=N).astype(np.uint32)
+    pay = np.arange(N, dtype=np.uint32)
+    k, p = oracle.sort(keys, pay, run_len)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(k, keys[order]) and np.array_equal(p, pay[order])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sort_dtypes(dtype):
+    g = np.random.default_rng(4)
+    keys = rand_sorted(g, 3000, 50, dtype)
+    keys = keys[g.permutation(3000)]
+    pay = g.integers(0, 2 ** 32, size=3000, dtype=np.uint64).astype(np.uint32)
+    k, p = oracle.sort(keys, pay, 64)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(k, keys[order]) and np.array_equal(p, pay[order])
+
+
+# --------------------------------------------------------------------------
+# O6: bounded exponential search
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("is_high", [False, True])
+def test_gallop_exact(is_high):
+    g = np.random.default_rng(12)
+    for _ in range(600):
+        n = int(g.integers(0, 300))
+        X = rand_sorted(g, n, int(g.integers(1, 60)), np.uint32)
+        x = rand_sorted(g, 1, 64, np.uint32)[0]
+        r = int(np.sum(X <= x)) if is_high else int(np.sum(X < x))
+        for e in (0, 1, -1, 2, -3, 7, -40, 1000, -1000):
+            for W in (0, 1, 4, 64, 1 << 20):
+                got, probes, fb = oracle.gallop(x, X, is_high, r + e, W)
+                assert got == r
+                g_cl = min(max(r + e, 0), n)
+                dist = abs(g_cl - r)
+                if W >= 2 * max(dist, 1):
+                    assert not fb
+                    # probe at g, gallop to at most 2*dist, bisect the bracket
+                    assert probes <= 2 + 2 * (dist.bit_length() + 1)
+                if fb:
+                    assert probes >= int(np.floor(np.log2(n + 1)))
+
+
+# --------------------------------------------------------------------------
+# O7: the predictor network
+# --------------------------------------------------------------------------
+
+def test_mlp_gradient_finite_differences():
+    g = np.random.default_rng(0)
+    phi = g.random(200)
+    target = np.sort(g.random(200))
+    params = g.normal(size=mlp.NPARAM)
+    L, grad = mlp.loss_and_grad(params, phi, target)
+    assert abs(L - mlp.loss(params, phi, target)) < 1e-15
+    h = 1e-6
+    for k in range(mlp.NPARAM):
+        e = np.zeros(mlp.NPARAM)
+        e[k] = h
+        fd = (mlp.loss(params + e, phi, target) - mlp.loss(params - e, phi, target)) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(grad[k])), k
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments, the first bias-corrected step is lr * g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    p0 = np.array([1.0, 1.0, 1.0, 1.0])
+    p1, m, v = mlp.adam_step(p0, g, np.zeros(4), np.zeros(4), 1, 0.01)
+    assert np.allclose(p1, p0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_mlp_features_order_preserving():
+    k32 = np.array([-2 ** 31, -1, 0, 1, 2 ** 31 - 1], dtype=np.int32)
+    f = mlp.features(k32)
+    assert (np.diff(f) > 0).all() and f[0] == 0.0
+    ku = np.array([0, 1, 2 ** 32 - 1], dtype=np.uint32)
+    assert np.isclose(mlp.features(ku)[-1], 1.0)
+
+
+def test_error_bins():
+    assert oracle.error_bin(0) == 32
+    assert oracle.error_bin(1) == 33 and oracle.error_bin(-1) == 31
+    assert oracle.error_bin(2) == 34 and oracle.error_bin(3) == 34 and oracle.error_bin(4) == 35
+    assert oracle.error_bin(-7) == 29 and oracle.error_bin(-8) == 28
+    assert oracle.error_bin(2 ** 40) == 64 and oracle.error_bin(-(2 ** 40)) == 0
+
+
+# --------------------------------------------------------------------------
+# A config-1 shaped case: heavy duplicates, p = 256
+# --------------------------------------------------------------------------
+
+def test_config1_shape_small():
+    g = np.random.default_rng(17)
+    A = np.sort(g.integers(0, 65536, size=200_000).astype(np.int32))
+    B = np.sort(g.integers(0, 65536, size=120_000).astype(np.int32))
+    pa = np.arange(len(A), dtype=np.uint32)
+    pb = np.arange(len(B), dtype=np.uint32) | np.uint32(1 << 31)
+    ak, ap = argsort_merge(A, B, pa, pb)
+    c, pc = oracle.merge(A, B, pa, pb)
+    assert np.array_equal(c, ak) and np.array_equal(pc, ap)
+    c, pc = oracle.merge_by_pieces(A, B, 256, 256, pa, pb)
+    assert np.array_equal(c, ak) and np.array_equal(pc, ap)
