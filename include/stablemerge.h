@@ -1,0 +1,146 @@
+/*
+ * stablemerge.h -- C ABI of libstablemerge.so, a stable parallel merge for
+ * AMD Instinct MI355X (gfx950), after J. L. Traeff, "Simplified, stable
+ * parallel merging" (arXiv:1202.6575).
+ *
+ * The method (Section 2): split the non-decreasing arrays A (n elements) and
+ * B (m elements) into blocks; compute the cross rank of every block's first
+ * element -- rank_low of an A element in B (Step 1), rank_high of a B
+ * element in A (Step 2); after one synchronisation, every block's processing
+ * element picks one of five cases and merges a disjoint pair of segments
+ * into its own range of C (Steps 3 and 4, Figure 2).  Equal keys keep A
+ * before B and each source keeps its own order (stability, Section 2).
+ *
+ * Conventions shared by every entry point:
+ *  - Every data pointer is a DEVICE pointer (HIP global memory) owned by the
+ *    caller.  The library never allocates, frees or retains caller memory.
+ *  - Keys of A and B are stored contiguously in one buffer: A = keys[0, n),
+ *    B = keys[n, n + m).  Payloads (optional, uint32) use the same layout.
+ *  - Key type (dtype): SM_INT32 compares as signed 32-bit, SM_UINT32 and
+ *    SM_UINT64 compare as unsigned.  Key, payload and output arrays passed to
+ *    the merge entry points must start on a 16-byte boundary (the kernels
+ *    move 16-byte chunks); the partition entry point needs element
+ *    alignment only.
+ *  - Every call that launches work is asynchronous on `stream` (a
+ *    hipStream_t, NULL = the default stream); host-side argument checks are
+ *    synchronous and return before anything is launched.
+ *  - Return value: SM_OK (0) or a negative sm_status; sm_last_error() gives
+ *    a message for the last failing call of the calling thread.  No C++
+ *    exception crosses this interface.
+ *  - Inputs must be non-decreasing under the key order (Section 2, problem
+ *    statement).  This is checked only when options.validate is set.
+ */
+#ifndef STABLEMERGE_H
+#define STABLEMERGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef SM_API
+#define SM_API __attribute__((visibility("default")))
+#endif
+
+typedef enum {
+    SM_INT32 = 0,
+    SM_UINT32 = 1,
+    SM_UINT64 = 2
+} sm_dtype;
+
+typedef enum {
+    SM_OK = 0,
+    SM_ERR_ARG = -1,        /* bad size, NULL pointer, misalignment, bad option */
+    SM_ERR_DTYPE = -2,      /* unknown key type */
+    SM_ERR_ALIAS = -3,      /* an output range overlaps an input range */
+    SM_ERR_WORKSPACE = -4,  /* workspace missing or smaller than required */
+    SM_ERR_HIP = -5,        /* a HIP runtime call or kernel launch failed */
+    SM_ERR_UNSORTED = -6    /* validate was set and an input is not sorted */
+} sm_status;
+
+/*
+ * Tuning and checking options; a NULL pointer or a zero field means "choose".
+ *  p_a, p_b   number of blocks of A and of B (Section 2, block decomposition).
+ *             0 = ceil(len / tile).  Forcing them reproduces the paper's
+ *             partition for a given p; the two may differ.
+ *  tile       block length in elements when p_a / p_b are 0.
+ *  validate   nonzero: first check that A and B are non-decreasing (one extra
+ *             read of the keys and a synchronisation with the host).
+ */
+typedef struct {
+    int64_t p_a;
+    int64_t p_b;
+    int32_t tile;
+    int32_t validate;
+    int32_t reserved[6];
+} sm_options;
+
+/* Message describing the last non-OK status returned on this thread. */
+SM_API const char *sm_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+SM_API int sm_version(void);
+
+/*
+ * Bytes of device workspace stable_merge needs for these arguments: the two
+ * cross-rank arrays of p_a + 1 and p_b + 1 int64 entries (Section 2, the
+ * synchronisation remark), a status word, and one 32-byte descriptor per
+ * subproblem.  Returns 0 on bad arguments.
+ */
+SM_API size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
+                                    const sm_options *opt);
+
+/*
+ * Stable merge of A = keys[0, n) and B = keys[n, n + m) into out_keys[0, n + m)
+ * (Section 2, Steps 1-4).  If payloads is not NULL, payloads[k] travels with
+ * keys[k] into out_payloads; payloads and out_payloads are both NULL or both
+ * non-NULL.  On equal keys every A element precedes every B element, and
+ * each source keeps its order.  n = 0 or m = 0 is valid; m > n is valid (the
+ * arrays are never swapped, which would change the tie order).
+ * Outputs must not overlap inputs (SM_ERR_ALIAS).  ws must hold at least
+ * stable_merge_workspace_bytes() bytes of device memory (SM_ERR_WORKSPACE).
+ * The result does not depend on p_a, p_b or tile: a stable merge is unique.
+ */
+SM_API int stable_merge(const void *keys, const uint32_t *payloads, int64_t n, int64_t m,
+                 void *out_keys, uint32_t *out_payloads, int dtype,
+                 void *ws, size_t ws_bytes, const sm_options *opt, void *stream);
+
+/*
+ * Steps 1 and 2 alone (Section 2): xbar[i] = rank_low(A[x_i], B) for
+ * 0 <= i < p_a with xbar[p_a] = m, and ybar[j] = rank_high(B[y_j], A) for
+ * 0 <= j < p_b with ybar[p_b] = n, where x_i and y_j are the block starts of
+ * the paper's block decomposition.  A block that is empty (len < p) starts at
+ * the +inf sentinel: its cross rank is m (resp. n).  xbar holds p_a + 1 and
+ * ybar p_b + 1 device int64 entries.  p_a, p_b >= 1.
+ */
+SM_API int stable_merge_partition(const void *keys, int64_t n, int64_t m, int64_t p_a, int64_t p_b,
+                           int dtype, int64_t *xbar, int64_t *ybar, void *stream);
+
+/*
+ * Steps 3 and 4 alone (Section 2): given the cross ranks xbar[0..p_a] and
+ * ybar[0..p_b] that stable_merge_partition wrote for the same keys, n, m,
+ * p_a, p_b and dtype, every block's processing element picks its case
+ * (a)-(e) and merges its subproblem into out_keys (and out_payloads).
+ * stable_merge_partition followed by this call on one stream is exactly
+ * stable_merge with forced p_a, p_b; the stream order is the method's single
+ * synchronisation.  Requires ceil(n/p_a) + ceil(m/p_b) to fit one
+ * workgroup (SM_ERR_ARG otherwise).  Same aliasing, alignment and payload
+ * rules as stable_merge.  ws (device, 16-byte aligned) receives the p_a + p_b
+ * subproblem descriptors and must hold stable_merge_pieces_workspace_bytes()
+ * bytes (SM_ERR_WORKSPACE otherwise).
+ */
+SM_API int stable_merge_pieces(const void *keys, const uint32_t *payloads, int64_t n, int64_t m,
+                               int64_t p_a, int64_t p_b, const int64_t *xbar, const int64_t *ybar,
+                               void *out_keys, uint32_t *out_payloads, int dtype,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* Device workspace bytes of stable_merge_pieces (0 on bad arguments). */
+SM_API size_t stable_merge_pieces_workspace_bytes(int64_t p_a, int64_t p_b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STABLEMERGE_H */

@@ -1,0 +1,172 @@
+"""Stable parallel merge for AMD MI355X (gfx950).
+
+Python binding of ``libstablemerge.so`` (C ABI in ``include/stablemerge.h``),
+after J. L. Traeff, "Simplified, stable parallel merging" (arXiv:1202.6575).
+
+This module only marshals arguments: it takes torch device tensors, passes
+their device pointers and the current HIP stream to the library, and turns
+negative status codes into exceptions.  Every step of the merge runs in the
+library's HIP kernels; there is no fallback path.  If the library is not
+built, importing this package raises.
+
+Keys layout: A = keys[0:n], B = keys[n:n+m] in one contiguous buffer.
+Supported key dtypes: torch.int32 (signed order), torch.uint32, torch.uint64.
+Payloads: optional torch.uint32 tensor with the same layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["merge", "partition", "merge_pieces", "workspace_bytes", "SMError", "LIB_PATH", "DTYPES"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstablemerge.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SM_INT32, SM_UINT32, SM_UINT64 = 0, 1, 2
+DTYPES = {torch.int32: SM_INT32, torch.uint32: SM_UINT32, torch.uint64: SM_UINT64}
+STATUS = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_DTYPE", -3: "SM_ERR_ALIAS",
+          -4: "SM_ERR_WORKSPACE", -5: "SM_ERR_HIP", -6: "SM_ERR_UNSORTED"}
+
+
+class SMError(RuntimeError):
+    """A negative status from libstablemerge; ``code`` holds it."""
+
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("p_a", ctypes.c_int64), ("p_b", ctypes.c_int64), ("tile", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+_vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+_lib.sm_last_error.restype = ctypes.c_char_p
+_lib.sm_last_error.argtypes = []
+_lib.sm_version.restype = _i32
+_lib.stable_merge_workspace_bytes.restype = _sz
+_lib.stable_merge_workspace_bytes.argtypes = [_i64, _i64, _i32, _i32, ctypes.POINTER(Options)]
+_lib.stable_merge.restype = _i32
+_lib.stable_merge.argtypes = [_vp, _vp, _i64, _i64, _vp, _vp, _i32, _vp, _sz,
+                              ctypes.POINTER(Options), _vp]
+_lib.stable_merge_pieces.restype = _i32
+_lib.stable_merge_pieces.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32,
+                                     _vp, _sz, _vp]
+_lib.stable_merge_pieces_workspace_bytes.restype = _sz
+_lib.stable_merge_pieces_workspace_bytes.argtypes = [_i64, _i64]
+_lib.stable_merge_partition.restype = _i32
+_lib.stable_merge_partition.argtypes = [_vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp]
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SMError(rc, _lib.sm_last_error().decode())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    try:
+        return DTYPES[t.dtype]
+    except KeyError:
+        raise SMError(-2, f"unsupported key dtype {t.dtype}") from None
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(p_a=0, p_b=0, tile=0, validate=False) -> Options:
+    return Options(int(p_a), int(p_b), int(tile), int(bool(validate)))
+
+
+def workspace_bytes(n: int, m: int, dtype: torch.dtype, has_payload: bool = False,
+                    p_a: int = 0, p_b: int = 0, tile: int = 0) -> int:
+    """Device workspace bytes stable_merge needs (0 on bad arguments)."""
+    o = _opts(p_a, p_b, tile)
+    return int(_lib.stable_merge_workspace_bytes(n, m, DTYPES[dtype], int(has_payload),
+                                                 ctypes.byref(o)))
+
+
+def _require_device(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise SMError(-1, "tensors must be contiguous device tensors")
+
+
+def merge(keys: torch.Tensor, n: int, m: int | None = None, payloads: torch.Tensor | None = None,
+          *, out_keys: torch.Tensor | None = None, out_payloads: torch.Tensor | None = None,
+          p_a: int = 0, p_b: int = 0, tile: int = 0, validate: bool = False,
+          workspace: torch.Tensor | None = None, stream=None):
+    """Stable merge of A = keys[:n] and B = keys[n:n+m] (Section 2, Steps 1-4).
+
+    Returns (out_keys, out_payloads); out_payloads is None without payloads.
+    Equal keys keep A before B; each source keeps its order."""
+    if m is None:
+        m = keys.numel() - n
+    if keys.numel() < n + m:
+        raise SMError(-1, "keys holds fewer than n + m elements")
+    _require_device(keys, payloads, out_keys, out_payloads, workspace)
+    code = _dtype_code(keys)
+    if out_keys is None:
+        out_keys = torch.empty(n + m, dtype=keys.dtype, device=keys.device)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(n + m, dtype=torch.uint32, device=keys.device)
+    o = _opts(p_a, p_b, tile, validate)
+    need = int(_lib.stable_merge_workspace_bytes(n, m, code, int(payloads is not None),
+                                                 ctypes.byref(o)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
+    _check(_lib.stable_merge(_ptr(keys), _ptr(payloads), n, m, _ptr(out_keys), _ptr(out_payloads),
+                             code, _ptr(workspace), workspace.numel(), ctypes.byref(o),
+                             _stream_ptr(stream)))
+    return out_keys, out_payloads
+
+
+def partition(keys: torch.Tensor, n: int, m: int, p_a: int, p_b: int | None = None, *,
+              xbar: torch.Tensor | None = None, ybar: torch.Tensor | None = None, stream=None):
+    """Steps 1-2: (xbar[p_a+1], ybar[p_b+1]) as device int64 tensors."""
+    p_b = p_a if p_b is None else p_b
+    _require_device(keys, xbar, ybar)
+    if xbar is None:
+        xbar = torch.empty(p_a + 1, dtype=torch.int64, device=keys.device)
+    if ybar is None:
+        ybar = torch.empty(p_b + 1, dtype=torch.int64, device=keys.device)
+    if xbar.numel() < p_a + 1 or ybar.numel() < p_b + 1 or xbar.dtype != torch.int64 \
+            or ybar.dtype != torch.int64:
+        raise SMError(-1, "xbar / ybar must be int64 with p_a + 1 / p_b + 1 entries")
+    _check(_lib.stable_merge_partition(_ptr(keys), n, m, p_a, p_b, _dtype_code(keys), _ptr(xbar),
+                                       _ptr(ybar), _stream_ptr(stream)))
+    return xbar, ybar
+
+
+def merge_pieces(keys: torch.Tensor, n: int, m: int, p_a: int, p_b: int, xbar: torch.Tensor,
+                 ybar: torch.Tensor, payloads: torch.Tensor | None = None, *,
+                 out_keys: torch.Tensor | None = None, out_payloads: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None, stream=None):
+    """Steps 3-4 given the cross ranks of ``partition`` for the same p_a, p_b."""
+    _require_device(keys, payloads, out_keys, out_payloads, xbar, ybar, workspace)
+    if workspace is None:
+        need = int(_lib.stable_merge_pieces_workspace_bytes(p_a, p_b))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
+    code = _dtype_code(keys)
+    if out_keys is None:
+        out_keys = torch.empty(n + m, dtype=keys.dtype, device=keys.device)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(n + m, dtype=torch.uint32, device=keys.device)
+    _check(_lib.stable_merge_pieces(_ptr(keys), _ptr(payloads), n, m, p_a, p_b, _ptr(xbar),
+                                    _ptr(ybar), _ptr(out_keys), _ptr(out_payloads), code,
+                                    _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+    return out_keys, out_payloads

@@ -1,0 +1,665 @@
+// sm_device.h -- device-side building blocks of the stable merge (gfx950).
+//
+// Block decomposition and membership (Section 2), binary-search ranks
+// rank_low / rank_high (Section 2 definitions), the two-select form of the
+// five cases of Steps 3-4, and the per-workgroup merge of one subproblem:
+// LDS staging with 128-bit loads, the same method again at lane level, a
+// per-lane stable sequential merge, and a coalesced write-back through LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sm {
+
+// ---------------------------------------------------------------------------
+// Block decomposition (Section 2): the first r = len mod p blocks hold
+// ceil(len/p) elements, the others floor(len/p).  start(i) = x_i with
+// x_p = len; of(k) is the block holding index k, with of(k) = p for k >= len
+// (the position of the +inf sentinel).
+// ---------------------------------------------------------------------------
+template <typename I>
+struct Blocks {
+    I len, p, q, r, c, rc;
+    __device__ __host__ Blocks(I len_, I p_) : len(len_), p(p_) {
+        q = len / p;
+        r = len - q * p;
+        c = q + (r != 0);
+        rc = r * c;
+    }
+    __device__ __host__ I start(I i) const {
+        if (i >= p) return len;
+        return i < r ? i * c : i * q + r;
+    }
+    __device__ __host__ I of(I k) const {
+        if (k >= len) return p;
+        return k < rc ? k / c : (k - rc) / q + r;
+    }
+};
+
+// Quotient k / d for 0 <= k < 2^22 and a workgroup-uniform divisor d >= 1
+// with rd = 1 / d: a float product, then one exact correction step.
+__device__ __forceinline__ int fast_div(int k, int d, float rd) {
+    int q = (int)((float)k * rd);
+    const int r = k - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
+
+// The same decomposition for the lane level: p = L blocks (a power of two),
+// lengths below 2^22, divisions by the uniform block sizes via fast_div.
+template <int L>
+struct LaneBlocks {
+    int len, q, r, c, rc;
+    float rcp_c, rcp_q;
+    static constexpr int p = L;
+    __device__ LaneBlocks(int len_) : len(len_) {
+        q = len / L;
+        r = len - q * L;
+        c = q + (r != 0);
+        rc = r * c;
+        rcp_c = c > 0 ? 1.0f / (float)c : 0.0f;
+        rcp_q = q > 0 ? 1.0f / (float)q : 0.0f;
+    }
+    __device__ int start(int i) const {
+        if (i >= L) return len;
+        return i < r ? i * c : i * q + r;
+    }
+    __device__ int of(int k) const {
+        if (k >= len) return L;
+        return k < rc ? fast_div(k, c, rcp_c) : fast_div(k - rc, q, rcp_q) + r;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Ranks by binary search (Section 2): rank_low(x, X) = #{X[t] < x},
+// rank_high(x, X) = #{X[t] <= x}, over X[0, len).
+// ---------------------------------------------------------------------------
+template <typename K, typename I>
+__device__ __forceinline__ I rank_low(const K* X, I len, K x) {
+    I lo = 0, n = len;
+    while (n > 0) {
+        I half = n >> 1;
+        if (X[lo + half] < x) { lo += half + 1; n -= half + 1; }
+        else n = half;
+    }
+    return lo;
+}
+
+template <typename K, typename I>
+__device__ __forceinline__ I rank_high(const K* X, I len, K x) {
+    I lo = 0, n = len;
+    while (n > 0) {
+        I half = n >> 1;
+        if (!(x < X[lo + half])) { lo += half + 1; n -= half + 1; }
+        else n = half;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3-4 in two-select form.  For the processing element of A block i:
+// outside case (e) (xbar_i != xbar_{i+1} and xbar_i = y_j) the B range ends
+// at min(xbar_{i+1}, y_{j+1}) and the A range at ybar_{j+1} if
+// xbar_{i+1} > y_{j+1}, else at x_{i+1}; this covers cases (a)-(d).
+// Case (e) takes A[x_i, ybar_j) alone.  B blocks mirror it with A and B,
+// rank_low and rank_high exchanged; the tie rule stays A before B.
+// The ybar / xbar arrays have p + 1 entries; indices are clamped so that a
+// block whose cross rank is the sentinel (j = p) never reads past them.
+// ---------------------------------------------------------------------------
+template <typename I>
+struct Piece {
+    I a_lo, a_hi, b_lo, b_hi, c_off;
+};
+
+template <typename I, typename BK, typename R>
+__device__ __forceinline__ Piece<I> step3_piece(const BK& BA, const BK& BB, const R* xbar,
+                                                const R* ybar, I i) {
+    Piece<I> s;
+    const I pb = (I)BB.p;
+    const I xi = BA.start(i), xi1 = BA.start(i + 1);
+    const I xb = (I)xbar[i], xb1 = (I)xbar[i + 1];
+    const I j = BB.of(xb);
+    const I yj = BB.start(j), yj1 = BB.start(j + 1);
+    const I j1 = j + 1 < pb ? j + 1 : pb;
+    s.a_lo = xi;
+    s.b_lo = xb;
+    s.c_off = xi + xb;
+    if (xb != xb1 && xb == yj) {
+        s.a_hi = (I)ybar[j < pb ? j : pb];
+        s.b_hi = xb;
+    } else {
+        s.b_hi = xb1 < yj1 ? xb1 : yj1;
+        s.a_hi = xb1 > yj1 ? (I)ybar[j1] : xi1;
+    }
+    return s;
+}
+
+template <typename I, typename BK, typename R>
+__device__ __forceinline__ Piece<I> step4_piece(const BK& BA, const BK& BB, const R* xbar,
+                                                const R* ybar, I j) {
+    Piece<I> s;
+    const I pa = (I)BA.p;
+    const I yj = BB.start(j), yj1 = BB.start(j + 1);
+    const I yb = (I)ybar[j], yb1 = (I)ybar[j + 1];
+    const I i = BA.of(yb);
+    const I xi = BA.start(i), xi1 = BA.start(i + 1);
+    const I i1 = i + 1 < pa ? i + 1 : pa;
+    s.b_lo = yj;
+    s.a_lo = yb;
+    s.c_off = yj + yb;
+    if (yb != yb1 && yb == xi) {
+        s.b_hi = (I)xbar[i < pa ? i : pa];
+        s.a_hi = yb;
+    } else {
+        s.a_hi = yb1 < xi1 ? yb1 : xi1;
+        s.b_hi = yb1 > xi1 ? (I)xbar[i1] : yj1;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access.  A buffer resource bounds every load to the valid bytes,
+// so the aligned 16-byte chunks that cover a segment never read past the
+// caller's array: out-of-range lanes read zero and are never used.
+// ---------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The base and size are workgroup-uniform; readfirstlane states that, so the
+// resource lives in scalar registers (no per-lane waterfall around loads).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+    const uint32_t nrec = bytes > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)bytes;
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    void* ub = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(nrec),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ u32x4 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// A subproblem in absolute element positions of the caller's arrays: merge
+// keys[ka0, ka0 + a) (from A) with keys[kb0, kb0 + b) (from B) into
+// out[out0, out0 + a + b).  Payloads use the same positions as their keys.
+// Bit 31 of a_f (b_f) is set when keys[ka0 + a] (keys[kb0 + b]) is the next
+// element of the same source array, i.e. the segment's successor exists.
+// Written by the case-selection kernel (Steps 3-4), read by the merge kernel.
+// ---------------------------------------------------------------------------
+struct PieceDesc {
+    int64_t ka0, kb0, out0;
+    uint32_t a_f, b_f;
+};
+constexpr uint32_t kSuccBit = 0x80000000u;
+__host__ __device__ inline int desc_a(const PieceDesc& d) { return (int)(d.a_f & ~kSuccBit); }
+__host__ __device__ inline int desc_b(const PieceDesc& d) { return (int)(d.b_f & ~kSuccBit); }
+
+template <typename K>
+struct Vec { static constexpr int N = 16 / sizeof(K); };
+
+template <typename K>
+struct KeyMax;
+template <> struct KeyMax<int32_t> { static constexpr int32_t v = 0x7fffffff; };
+template <> struct KeyMax<uint32_t> { static constexpr uint32_t v = 0xffffffffu; };
+template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = ~0ull; };
+
+// rank_low / rank_high of x over X[0, n) in LDS, branch-free (the halving
+// length is workgroup-uniform, so only the base moves per lane): the answer
+// stays in [base, base + len] while len halves.
+template <typename K>
+__device__ __forceinline__ int lower_bound_lds(const K* X, int n, K x) {
+    if (n <= 0) return 0;
+    int base = 0;
+    for (int len = n; len > 1;) {
+        const int half = len >> 1;
+        base = X[base + half] < x ? base + half : base;
+        len -= half;
+    }
+    return base + (X[base] < x ? 1 : 0);
+}
+
+template <typename K>
+__device__ __forceinline__ int upper_bound_lds(const K* X, int n, K x) {
+    if (n <= 0) return 0;
+    int base = 0;
+    for (int len = n; len > 1;) {
+        const int half = len >> 1;
+        base = !(x < X[base + half]) ? base + half : base;
+        len -= half;
+    }
+    return base + (!(x < X[base]) ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup merge of one subproblem, in phases:
+//   plan     uniform window geometry of the A and B segments and of C
+//   prefetch 16-byte chunk loads of both windows into registers (the loads
+//            stay in flight while the workgroup merges the previous piece)
+//   commit   registers -> LDS
+//   merge    lane-level cross ranks, per-lane merges, write-back
+//
+// LDS layout (slot = one key):
+//   sKey[0, wa)            A window: 16-byte chunks from A's aligned start,
+//                          A[i] at slot offA + i, successor at offA + a
+//   sKey[wa, wa + nb*V)    B window, B[j] at slot wa + offB + j, successor
+//                          at wa + offB + b
+//   sPay                   payload windows, A[i] at offPA + i, B[j] at
+//                          waP + offPB + j
+//   sOut                   merged keys, output k at offC + k
+//   sIdx                   payload case: key slot of output k at offCP + k,
+//                          then (after the gather) its payload
+//   sXb[L+1], sYb[L+1]     lane-level cross ranks
+//
+// Lane level: the workgroup is p = L processing elements.  The A and B
+// segments are split into L blocks each (the paper's block decomposition);
+// lane t computes xbar_t = rank_low(A[x_t], B) and ybar_t = rank_high(B[y_t], A)
+// by binary search in LDS; after one barrier it merges its Step-3 subproblem
+// and its Step-4 subproblem with a sequential stable merge (take B only if
+// strictly smaller), writing each output to its slot in LDS.  After a second
+// barrier the workgroup writes C with aligned 16-byte stores, and element
+// stores at the two partial ends.
+//
+// Sentinels.  In every case of Steps 3-4 the element right after a
+// subproblem's A range is strictly greater than all of its B elements, and
+// the element right after its B range is greater than or equal to all of its
+// A elements (both follow from the cross-rank definitions).  So when one side
+// runs out, its next element steers the comparison "take B iff B < A" to the
+// other side, and the merge loop needs no bounds checks.  The windows stage
+// one element past each segment for this.  Where a segment ends its array,
+// the slot holds the key type's maximum: correct for the B side always, and
+// for the A side unless the segment's B part contains that maximum -- then
+// the workgroup uses the bounds-checked loop instead.
+// ---------------------------------------------------------------------------
+template <typename K, bool PAY, int L>
+struct MergeSmem {
+    // a lane keeps merging past its own range until the slowest lane of its
+    // wave is done (at most one lane subproblem, ceil(cap / L) + 1 elements),
+    // so key and output slots carry that much slack past the subproblem
+    static __host__ __device__ uint32_t slack(uint32_t cap) { return 2 * ((cap + L - 1) / L) + 16; }
+    static __host__ __device__ uint32_t key_slots(uint32_t cap) {
+        return (cap + 4 * Vec<K>::N + 8 + slack(cap) + 7) & ~7u;
+    }
+    static __host__ __device__ uint32_t pay_slots(uint32_t cap) { return (cap + 24 + 7) & ~7u; }
+    static __host__ __device__ uint32_t out_slots(uint32_t cap) {
+        return (cap + Vec<K>::N + 8 + slack(cap) + 7) & ~7u;
+    }
+    static __host__ __device__ uint32_t bytes(uint32_t cap) {
+        uint32_t b = key_slots(cap) * sizeof(K) + out_slots(cap) * sizeof(K);
+        if (PAY) b += pay_slots(cap) * 4 + out_slots(cap) * 4;
+        b += 2 * (L + 1) * 4;
+        return (b + 15) & ~15u;
+    }
+};
+
+struct SegPlan {
+    int a, b, s;
+    int offA, offB, wa, nca, ncb;      // key windows (chunks of V keys)
+    int offPA, offPB, waP, ncpa, ncpb; // payload windows (chunks of 4)
+    int offC, offCP;                   // alignment of the outputs
+    int qsA, esA, qsB, esB;            // chunk / element holding each successor slot
+    bool succA, succB;                 // successor present in the source array
+    int64_t ka_al, kb_al, c0;          // aligned absolute starts, output start
+};
+
+template <typename K, bool PAY>
+__device__ __forceinline__ SegPlan make_plan(const PieceDesc& d) {
+    constexpr int V = Vec<K>::N;
+    SegPlan p;
+    p.a = desc_a(d);
+    p.b = desc_b(d);
+    p.s = p.a + p.b;
+    p.succA = (d.a_f & kSuccBit) != 0;
+    p.succB = (d.b_f & kSuccBit) != 0;
+    // arrays start 16-byte aligned, so alignment follows from the index
+    p.offA = (int)(d.ka0 & (V - 1));
+    p.offB = (int)(d.kb0 & (V - 1));
+    p.ka_al = d.ka0 - p.offA;
+    p.kb_al = d.kb0 - p.offB;
+    // one extra slot per window for the successor
+    p.nca = (p.offA + p.a + 1 + V - 1) / V;
+    p.ncb = (p.offB + p.b + 1 + V - 1) / V;
+    p.wa = p.nca * V;
+    p.qsA = (p.offA + p.a) / V;
+    p.esA = (p.offA + p.a) % V;
+    p.qsB = p.nca + (p.offB + p.b) / V;
+    p.esB = (p.offB + p.b) % V;
+    p.offPA = (int)(d.ka0 & 3);
+    p.offPB = (int)(d.kb0 & 3);
+    p.ncpa = PAY ? (p.offPA + p.a + 3) / 4 : 0;
+    p.ncpb = PAY ? (p.offPB + p.b + 3) / 4 : 0;
+    p.waP = p.ncpa * 4;
+    p.c0 = d.out0;
+    p.offC = (int)(d.out0 & (V - 1));
+    p.offCP = (int)(d.out0 & 3);
+    return p;
+}
+
+// Issue the 16-byte loads of two windows into registers: chunk q goes to
+// rk[q / L] of thread q % L (first window first).  Every slot is loaded
+// unconditionally; slots past both windows use an offset beyond the buffer
+// resource's range, which returns zeros without a memory access.  (A
+// conditional load would have to merge with the register's previous value,
+// making the load wait for everything in flight, stores included.)  When both
+// windows lie within 4 GiB of the lower one, one resource based there serves
+// both; otherwise each window gets its own and every slot issues two loads.
+constexpr uint32_t kOffNone = 0xFFFFFFF0u;
+
+template <int L, int R>
+__device__ __forceinline__ void load_windows(const char* base, uint64_t bytes_to_end, int64_t wa0,
+                                             int na, int64_t wb0, int nb, u32x4 (&rk)[R]) {
+    const int t = threadIdx.x;
+    const int64_t lo = wa0 < wb0 ? wa0 : wb0;
+    const int64_t hi = (wa0 + 16ll * na) > (wb0 + 16ll * nb) ? (wa0 + 16ll * na) : (wb0 + 16ll * nb);
+    if (hi - lo <= 0xFFFFFF00ll) {
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(base + lo, bytes_to_end - (uint64_t)lo);
+        const uint32_t oa = (uint32_t)(wa0 - lo), ob = (uint32_t)(wb0 - lo);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int q = i * L + t;
+            const uint32_t off = q < na ? oa + q * 16 : (q < na + nb ? ob + (q - na) * 16 : kOffNone);
+            rk[i] = buf_load16(r, off);
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t rA = make_rsrc(base + wa0, bytes_to_end - (uint64_t)wa0);
+        const __amdgpu_buffer_rsrc_t rB = make_rsrc(base + wb0, bytes_to_end - (uint64_t)wb0);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int q = i * L + t;
+            const u32x4 va = buf_load16(rA, q < na ? q * 16 : kOffNone);
+            const u32x4 vb = buf_load16(rB, q >= na && q < na + nb ? (q - na) * 16 : kOffNone);
+            rk[i] = q < na ? va : vb;
+        }
+    }
+}
+
+template <typename K, bool PAY, int L, int R>
+__device__ __forceinline__ void prefetch(const SegPlan& p, const K* keys, uint64_t nkeys,
+                                         const uint32_t* pay, u32x4 (&rk)[R], u32x4 (&rp)[R]) {
+    load_windows<L, R>(reinterpret_cast<const char*>(keys), nkeys * sizeof(K),
+                       p.ka_al * (int64_t)sizeof(K), p.nca, p.kb_al * (int64_t)sizeof(K), p.ncb, rk);
+    if (PAY)
+        load_windows<L, R>(reinterpret_cast<const char*>(pay), nkeys * 4,
+                           (p.ka_al + p.offA - p.offPA) * 4, p.ncpa,
+                           (p.kb_al + p.offB - p.offPB) * 4, p.ncpb, rp);
+}
+
+// Key chunk q after the successor fix-up: a successor slot whose segment
+// ends its source array holds the key type's maximum.
+template <typename K>
+__device__ __forceinline__ u32x4 fix_successor(const SegPlan& p, int q, u32x4 v) {
+    K* e = reinterpret_cast<K*>(&v);
+    if (q == p.qsA && !p.succA) e[p.esA] = KeyMax<K>::v;
+    if (q == p.qsB && !p.succB) e[p.esB] = KeyMax<K>::v;
+    return v;
+}
+
+template <typename K, bool PAY, int L, int R>
+__device__ __forceinline__ void commit(const SegPlan& p, const u32x4 (&rk)[R],
+                                       const u32x4 (&rp)[R], K* sKey, uint32_t* sPay) {
+    constexpr int V = Vec<K>::N;
+    const int t = threadIdx.x;
+    // one explicit wait for everything in flight (this piece's loads, and
+    // stores issued a whole merge ago): afterwards no register has a load
+    // pending, so the compiler adds no waits further down the iteration
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = r * L + t;
+        if (q < p.nca + p.ncb) {
+            const u32x4 v = fix_successor<K>(p, q, rk[r]);
+            *reinterpret_cast<u32x4*>(sKey + (q < p.nca ? q * V : p.wa + (q - p.nca) * V)) = v;
+        }
+    }
+    if (PAY) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int q = r * L + t;
+            if (q < p.ncpa + p.ncpb)
+                *reinterpret_cast<u32x4*>(sPay + (q < p.ncpa ? q * 4 : p.waP + (q - p.ncpa) * 4)) = rp[r];
+        }
+    }
+}
+
+// Direct staging (no register prefetch) for subproblems too large for the
+// register-pipelined path: chunk loop straight from global memory to LDS.
+template <typename K, bool PAY, int L>
+__device__ __forceinline__ void stage_direct(const SegPlan& p, const K* keys, uint64_t nkeys,
+                                             const uint32_t* pay, K* sKey, uint32_t* sPay) {
+    constexpr int V = Vec<K>::N;
+    const int t = threadIdx.x;
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(keys + p.ka_al, (nkeys - p.ka_al) * sizeof(K));
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(keys + p.kb_al, (nkeys - p.kb_al) * sizeof(K));
+    for (int q = t; q < p.nca + p.ncb; q += L) {
+        if (q < p.nca)
+            *reinterpret_cast<u32x4*>(sKey + q * V) = fix_successor<K>(p, q, buf_load16(rA, q * 16));
+        else
+            *reinterpret_cast<u32x4*>(sKey + p.wa + (q - p.nca) * V) =
+                fix_successor<K>(p, q, buf_load16(rB, (q - p.nca) * 16));
+    }
+    if (PAY) {
+        const __amdgpu_buffer_rsrc_t qA = make_rsrc(pay + (p.ka_al + p.offA - p.offPA),
+                                                    (nkeys - (p.ka_al + p.offA - p.offPA)) * 4);
+        const __amdgpu_buffer_rsrc_t qB = make_rsrc(pay + (p.kb_al + p.offB - p.offPB),
+                                                    (nkeys - (p.kb_al + p.offB - p.offPB)) * 4);
+        for (int q = t; q < p.ncpa + p.ncpb; q += L) {
+            if (q < p.ncpa) *reinterpret_cast<u32x4*>(sPay + q * 4) = buf_load16(qA, q * 16);
+            else *reinterpret_cast<u32x4*>(sPay + p.waP + (q - p.ncpa) * 4) = buf_load16(qB, (q - p.ncpa) * 16);
+        }
+    }
+}
+
+// Sequential stable merge of one lane subproblem: A slots from ia, B slots
+// from ib, la + lb outputs at slots from co.
+//
+// Uniform form (sentinels valid): every lane of the wave runs the same number
+// of steps, the largest la + lb in the wave.  A lane that is done keeps
+// merging: its start (ia, ib) is a prefix state of the stable merge (the
+// outputs before c_off are exactly A[0, a_lo) and B[0, b_lo)), so its extra
+// outputs are the true next outputs -- the same values the lanes owning those
+// slots write -- or lie past the subproblem, in slack slots nobody reads.
+// Reads stay valid until the lane has output the whole subproblem: the
+// successors stand in for the element after each segment.
+template <typename K, bool PAY>
+__device__ __forceinline__ void lane_merge_uniform(const K* sKey, K* sOut, uint32_t* sIdx, int ia,
+                                                   int ib, int len, int co, int cp) {
+    if (!__any(len > 0)) return;
+    K ka = sKey[ia];
+    K kb = sKey[ib];
+    int k = 0;
+    do {
+        const bool takeB = kb < ka;
+        const int src = takeB ? ib : ia;
+        sOut[co + k] = takeB ? kb : ka;
+        if (PAY) sIdx[cp + k] = (uint32_t)src;
+        const int nxt = src + 1;
+        const K kn = sKey[nxt];
+        ib = takeB ? nxt : ib;
+        ia = takeB ? ia : nxt;
+        kb = takeB ? kn : kb;
+        ka = takeB ? ka : kn;
+        ++k;
+    } while (__any(k < len));
+}
+
+// Bounds-checked form: each lane stops after its own la + lb outputs.
+template <typename K, bool PAY>
+__device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint32_t* sIdx, int ia,
+                                                   int la, int ib, int lb, int co, int cp) {
+    const int len = la + lb;
+    const int ea = ia + la, eb = ib + lb;
+    K ka = sKey[ia];
+    K kb = sKey[ib];
+    for (int k = 0; k < len; ++k) {
+        const bool takeB = (ib < eb) && (ia >= ea || kb < ka);
+        const int src = takeB ? ib : ia;
+        sOut[co + k] = takeB ? kb : ka;
+        if (PAY) sIdx[cp + k] = (uint32_t)src;
+        const int nxt = src + 1;
+        const K kn = sKey[nxt];
+        if (takeB) { ib = nxt; kb = kn; }
+        else { ia = nxt; ka = kn; }
+    }
+}
+
+// Lane-level split and per-lane merges of a staged subproblem.  Entered by
+// the whole workgroup after a barrier that follows commit / stage_direct;
+// ends after a barrier, with output k in sOut[offC + k] (and, with payloads,
+// its payload in sIdx[offCP + k]).  The staging buffers are free afterwards.
+template <typename K, bool PAY, int L>
+__device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, const uint32_t* sPay,
+                                            K* sOut, uint32_t* sIdx, int* sXb, int* sYb) {
+    const int t = threadIdx.x;
+    const int a = p.a, b = p.b, s = p.s;
+    const int baseA = p.offA, baseB = p.wa + p.offB;
+
+    // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
+    const LaneBlocks<L> LA(a), LB(b);
+    {
+        const int xt = LA.start(t);
+        sXb[t] = xt < a ? lower_bound_lds<K>(sKey + baseB, b, sKey[baseA + xt]) : b;
+        const int yt = LB.start(t);
+        sYb[t] = yt < b ? upper_bound_lds<K>(sKey + baseA, a, sKey[baseB + yt]) : a;
+        if (t == 0) {
+            sXb[L] = b;
+            sYb[L] = a;
+        }
+    }
+    __syncthreads();
+
+    // the sentinel loop is exact unless the A successor is the type maximum
+    // and the B part holds that maximum too
+    const bool fast = p.succA || b == 0 || sKey[baseB + b - 1] != KeyMax<K>::v;
+
+    // ---- per-lane stable sequential merges (Steps 3-4 inside the WG) ------
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+        const Piece<int> pc = side == 0 ? step3_piece<int>(LA, LB, sXb, sYb, t)
+                                        : step4_piece<int>(LA, LB, sXb, sYb, t);
+        // a descriptor outside the segment would be a bug; it merges nothing
+        const bool ok = 0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= a && 0 <= pc.b_lo &&
+                        pc.b_lo <= pc.b_hi && pc.b_hi <= b && 0 <= pc.c_off &&
+                        pc.c_off + (pc.a_hi - pc.a_lo) + (pc.b_hi - pc.b_lo) <= s;
+        const int la = ok ? pc.a_hi - pc.a_lo : 0, lb = ok ? pc.b_hi - pc.b_lo : 0;
+        if (fast)
+            lane_merge_uniform<K, PAY>(sKey, sOut, sIdx, baseA + pc.a_lo, baseB + pc.b_lo, la + lb,
+                                       p.offC + pc.c_off, p.offCP + pc.c_off);
+        else
+            lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + pc.a_lo, la, baseB + pc.b_lo, lb,
+                                       p.offC + pc.c_off, p.offCP + pc.c_off);
+    }
+    __syncthreads();
+
+    if (PAY) {
+        // gather: key slot of each output -> its payload (same element in the
+        // payload window geometry), in place
+        for (int k = t; k < s; k += L) {
+            const int si = (int)sIdx[p.offCP + k];
+            const int ps = si < p.wa ? si - p.offA + p.offPA : si - p.wa - p.offB + p.waP + p.offPB;
+            sIdx[p.offCP + k] = sPay[ps];
+        }
+        __syncthreads();
+    }
+}
+
+// Write-back of merged outputs: aligned 16-byte stores for whole chunks,
+// element stores at the two partial ends.  Reads only sOut / sIdx, so it
+// may run after the staging buffers have been refilled.  RW = number of
+// output chunks per thread, unrolled (0 = a loop, for large subproblems).
+template <typename K, bool PAY, int L, int RW>
+__device__ __forceinline__ void write_back(const SegPlan& p, const K* sOut, const uint32_t* sIdx,
+                                           K* out, uint32_t* out_pay) {
+    constexpr int V = Vec<K>::N;
+    const int t = threadIdx.x;
+    const int s = p.s;
+    if (s == 0) return;
+    K* baseC = out + (p.c0 - p.offC);
+    const int ncc = (p.offC + s + V - 1) / V;
+    auto key_chunk = [&](int q) {
+        const int lo = q * V;
+        if (lo >= p.offC && lo + V <= p.offC + s) {
+            *reinterpret_cast<u32x4*>(baseC + lo) = *reinterpret_cast<const u32x4*>(sOut + lo);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int k = lo + e;
+                if (k >= p.offC && k < p.offC + s) baseC[k] = sOut[k];
+            }
+        }
+    };
+    if (RW > 0) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int q = r * L + t;
+            if (q < ncc) key_chunk(q);
+        }
+    } else {
+        for (int q = t; q < ncc; q += L) key_chunk(q);
+    }
+    if (PAY) {
+        uint32_t* baseP = out_pay + (p.c0 - p.offCP);
+        const int ncp = (p.offCP + s + 3) / 4;
+        auto pay_chunk = [&](int q) {
+            const int lo = q * 4;
+            if (lo >= p.offCP && lo + 4 <= p.offCP + s) {
+                *reinterpret_cast<u32x4*>(baseP + lo) = *reinterpret_cast<const u32x4*>(sIdx + lo);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = lo + e;
+                    if (k >= p.offCP && k < p.offCP + s) baseP[k] = sIdx[k];
+                }
+            }
+        };
+        if (RW > 0) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int q = r * L + t;
+                if (q < ncp) pay_chunk(q);
+            }
+        } else {
+            for (int q = t; q < ncp; q += L) pay_chunk(q);
+        }
+    }
+}
+
+// LDS carve-up shared by the merge kernels.
+template <typename K, bool PAY, int L>
+struct SmemPtrs {
+    K* sKey;
+    uint32_t* sPay;
+    K* sOut;
+    uint32_t* sIdx;
+    int* sXb;
+    int* sYb;
+    __device__ SmemPtrs(char* smem, uint32_t cap) {
+        using M = MergeSmem<K, PAY, L>;
+        char* p = smem;
+        sKey = reinterpret_cast<K*>(p);
+        p += M::key_slots(cap) * sizeof(K);
+        sOut = reinterpret_cast<K*>(p);
+        p += M::out_slots(cap) * sizeof(K);
+        sPay = nullptr;
+        sIdx = nullptr;
+        if (PAY) {
+            sPay = reinterpret_cast<uint32_t*>(p);
+            p += M::pay_slots(cap) * 4;
+            sIdx = reinterpret_cast<uint32_t*>(p);
+            p += M::out_slots(cap) * 4;
+        }
+        sXb = reinterpret_cast<int*>(p);
+        sYb = sXb + (L + 1);
+    }
+};
+
+// A descriptor is usable if it lies inside the arrays and fits the LDS.
+__device__ __forceinline__ bool desc_ok(const PieceDesc& d, int64_t nkeys, int64_t nout,
+                                        uint32_t cap) {
+    const int64_t a = desc_a(d), b = desc_b(d);
+    return a + b <= (int64_t)cap && d.ka0 >= 0 && d.ka0 + a <= nkeys && d.kb0 >= 0 &&
+           d.kb0 + b <= nkeys && d.out0 >= 0 && d.out0 + a + b <= nout;
+}
+
+}  // namespace sm

@@ -1,0 +1,48 @@
+// sm_launch.h -- host-side launchers of the stable-merge kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sm {
+
+// Workgroup size of the merge kernels: p = 256 lane-level processing elements.
+constexpr int kMergeThreads = 256;
+// Largest dynamic LDS a merge workgroup may use (gfx950: 160 KiB per CU).
+constexpr uint32_t kMaxLds = 160 * 1024;
+
+// LDS bytes a merge workgroup needs for subproblems of up to cap elements.
+uint32_t merge_lds_bytes(int dtype, bool pay, uint32_t cap);
+
+// Steps 1-2: xbar[0..p_a], ybar[0..p_b] (int64, device).
+hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m,
+                            int64_t p_a, int64_t p_b, int64_t* xbar, int64_t* ybar,
+                            hipStream_t st);
+
+struct PieceDesc;
+
+// Steps 3-4 plus the merges: the case-selection kernel writes p_a + p_b
+// descriptors into desc, then the merge kernel merges them.
+hipError_t launch_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n, int64_t m,
+                        int64_t p_a, int64_t p_b, const int64_t* xbar, const int64_t* ybar,
+                        PieceDesc* desc, void* out_keys, uint32_t* out_pay, uint32_t cap,
+                        hipStream_t st);
+
+// Steps 3-4 case selection alone.
+hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
+                        const int64_t* ybar, PieceDesc* desc, hipStream_t st);
+
+// Merges of P subproblem descriptors (keys / payload positions index arrays
+// of nkeys elements; outputs index arrays of nout elements).
+hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
+                             void* out_keys, uint32_t* out_pay, int64_t nout,
+                             const PieceDesc* desc, int64_t P, uint32_t cap, hipStream_t st);
+
+constexpr size_t kPieceDescBytes = 32;
+
+// Sets *flag (device int) to 1 if keys[0, n) or keys[n, n + m) is not
+// non-decreasing; *flag must be 0 before the launch.
+hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, int* flag,
+                           hipStream_t st);
+
+}  // namespace sm

@@ -1,0 +1,293 @@
+// sm_merge.hip -- the plain stable merge on gfx950.
+//
+// K1 partition_kernel: Steps 1-2 of Section 2, one lane per block start, a
+//    binary search in global memory per lane.  The kernel boundary is the
+//    method's single synchronisation.
+// K2 cases_kernel: Steps 3-4 case selection, one thread per subproblem,
+//    writes a descriptor (the five cases in two-select form).
+// K3 merge_persistent_kernel / merge_direct_kernel: the merges, one
+//    workgroup per subproblem at a time (the workgroup merge of sm_device.h).
+#include "sm_device.h"
+#include "sm_launch.h"
+
+namespace sm {
+
+template <typename K>
+__global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ keys, int64_t n,
+                                                        int64_t m, int64_t p_a, int64_t p_b,
+                                                        int64_t* __restrict__ xbar,
+                                                        int64_t* __restrict__ ybar) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const K* A = keys;
+    const K* B = keys + n;
+    if (t <= p_a) {
+        const Blocks<int64_t> BA(n, p_a);
+        const int64_t xi = BA.start(t);
+        xbar[t] = xi < n ? rank_low<K, int64_t>(B, m, A[xi]) : m;
+    } else if (t <= p_a + 1 + p_b) {
+        const int64_t j = t - (p_a + 1);
+        const Blocks<int64_t> BB(m, p_b);
+        const int64_t yj = BB.start(j);
+        ybar[j] = yj < m ? rank_high<K, int64_t>(A, n, B[yj]) : n;
+    }
+}
+
+// Steps 3-4 case selection: one thread per subproblem writes its descriptor
+// (the five cases in two-select form).  Subproblems 0..p_a-1 belong to the
+// processing elements of A blocks (Step 3), p_a..p_a+p_b-1 to B blocks
+// (Step 4).  The output position of every subproblem is a_lo + b_lo (the
+// stable-merge position identity of Section 2).
+__global__ __launch_bounds__(256) void cases_kernel(int64_t n, int64_t m, int64_t p_a,
+                                                    int64_t p_b, const int64_t* __restrict__ xbar,
+                                                    const int64_t* __restrict__ ybar,
+                                                    PieceDesc* __restrict__ desc) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= p_a + p_b) return;
+    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
+    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
+                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
+    PieceDesc d;
+    d.ka0 = pc.a_lo;
+    d.kb0 = n + pc.b_lo;
+    d.out0 = pc.a_lo + pc.b_lo;
+    // a subproblem outside the arrays would be a bug: it is emptied, so the
+    // merge kernel never writes outside C (the output is then wrong, not unsafe)
+    if (!(0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= n && 0 <= pc.b_lo &&
+          pc.b_lo <= pc.b_hi && pc.b_hi <= m && pc.a_hi - pc.a_lo < (1 << 30) &&
+          pc.b_hi - pc.b_lo < (1 << 30))) {
+        d.a_f = 0;
+        d.b_f = 0;
+    } else {
+        d.a_f = (uint32_t)(pc.a_hi - pc.a_lo) | (pc.a_hi < n ? kSuccBit : 0u);
+        d.b_f = (uint32_t)(pc.b_hi - pc.b_lo) | (pc.b_hi < m ? kSuccBit : 0u);
+    }
+    desc[w] = d;
+}
+
+// Persistent merge: workgroup g merges subproblems [g*P/G, (g+1)*P/G) in order.
+// While it merges subproblem w, the 16-byte loads of subproblem w+1 are in
+// flight in registers (R chunks per thread) and the stores of subproblem w-1
+// are draining.
+template <typename K, bool PAY, int L, int R>
+__global__ __launch_bounds__(L) void merge_persistent_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
+    const PieceDesc* __restrict__ desc, int64_t P, uint32_t cap) {
+    extern __shared__ __align__(16) char smem[];
+    const SmemPtrs<K, PAY, L> sp(smem, cap);
+    const int64_t G = gridDim.x;
+    const int64_t w0 = (int64_t)blockIdx.x * P / G;
+    const int64_t w1 = ((int64_t)blockIdx.x + 1) * P / G;
+    if (w0 >= w1) return;
+    u32x4 rk[R], rp[R];
+    PieceDesc d = desc[w0];
+    if (!desc_ok(d, nkeys, nout, cap)) d.a_f = d.b_f = 0;
+    SegPlan cur = make_plan<K, PAY>(d);
+    SegPlan prev = cur;
+    prefetch<K, PAY, L, R>(cur, keys, (uint64_t)nkeys, pay, rk, rp);
+    for (int64_t w = w0; w < w1; ++w) {
+        const bool more = w + 1 < w1;
+        PieceDesc dn;
+        dn.ka0 = dn.kb0 = dn.out0 = 0;
+        dn.a_f = dn.b_f = 0;
+        if (more) {
+            dn = desc[w + 1];
+            if (!desc_ok(dn, nkeys, nout, cap)) dn.a_f = dn.b_f = 0;
+        }
+        const SegPlan nxt = make_plan<K, PAY>(dn);
+        // Order: wait for this piece's loads (commit), issue the next piece's
+        // loads, then the previous piece's stores, then merge.  Stores and loads
+        // share one completion counter, so nothing waits on a store until the
+        // next commit, a whole merge later.  The write-back reads sOut / sIdx,
+        // which this piece's merge rewrites only after its first barrier.
+        commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
+        __syncthreads();
+        if (more) prefetch<K, PAY, L, R>(nxt, keys, (uint64_t)nkeys, pay, rk, rp);
+        if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+        if (cur.s > 0) merge_lanes<K, PAY, L>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
+        prev = cur;
+        cur = nxt;
+    }
+    write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+}
+
+// One workgroup per subproblem, staged straight into LDS; for subproblems
+// larger than the register-pipelined kernel holds.
+template <typename K, bool PAY, int L>
+__global__ __launch_bounds__(L) void merge_direct_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
+    const PieceDesc* __restrict__ desc, int64_t P, uint32_t cap) {
+    extern __shared__ __align__(16) char smem[];
+    const SmemPtrs<K, PAY, L> sp(smem, cap);
+    const PieceDesc d = desc[blockIdx.x];
+    if (!desc_ok(d, nkeys, nout, cap) || desc_a(d) + desc_b(d) == 0) return;
+    const SegPlan p = make_plan<K, PAY>(d);
+    stage_direct<K, PAY, L>(p, keys, (uint64_t)nkeys, pay, sp.sKey, sp.sPay);
+    __syncthreads();
+    merge_lanes<K, PAY, L>(p, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
+    write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void validate_kernel(const K* __restrict__ keys, int64_t n,
+                                                       int64_t m, int* flag) {
+    const int64_t total = n + m;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k + 1 < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (k + 1 == n) continue;  // boundary between A and B
+        if (keys[k + 1] < keys[k]) *flag = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename F>
+static void with_dtype(int dtype, F&& f) {
+    if (dtype == 0) f((int32_t)0);
+    else if (dtype == 1) f((uint32_t)0);
+    else f((uint64_t)0);
+}
+
+uint32_t merge_lds_bytes(int dtype, bool pay, uint32_t cap) {
+    uint32_t r = 0;
+    with_dtype(dtype, [&](auto z) {
+        using K = decltype(z);
+        r = pay ? MergeSmem<K, true, kMergeThreads>::bytes(cap)
+                : MergeSmem<K, false, kMergeThreads>::bytes(cap);
+    });
+    return r;
+}
+
+hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m, int64_t p_a,
+                            int64_t p_b, int64_t* xbar, int64_t* ybar, hipStream_t st) {
+    const int64_t threads = p_a + p_b + 2;
+    const unsigned grid = (unsigned)((threads + 255) / 256);
+    with_dtype(dtype, [&](auto z) {
+        using K = decltype(z);
+        partition_kernel<K><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), n, m, p_a, p_b,
+                                                  xbar, ybar);
+    });
+    return hipGetLastError();
+}
+
+static int cu_count() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <typename Kern>
+static hipError_t allow_big_lds(Kern kern) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+}
+
+// Largest subproblem the register-pipelined kernel with R chunks per thread
+// can stage: key chunks <= cap / V + 4 and payload chunks <= cap / 4 + 4 must
+// not exceed R * L.
+template <typename K, bool PAY>
+static bool fits_regs(uint32_t cap, int R) {
+    constexpr int V = Vec<K>::N;
+    const int64_t slots = (int64_t)R * kMergeThreads;
+    if ((int64_t)cap / V + 5 > slots) return false;
+    if (PAY && (int64_t)cap / 4 + 4 > slots) return false;
+    return true;
+}
+
+template <typename K, bool PAY, int R>
+static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t nkeys, K* out,
+                                    uint32_t* out_pay, int64_t nout, const PieceDesc* desc,
+                                    int64_t P, uint32_t cap, hipStream_t st) {
+    constexpr int L = kMergeThreads;
+    auto kern = merge_persistent_kernel<K, PAY, L, R>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = allow_big_lds(kern);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
+    int per_cu = (int)(kMaxLds / lds);
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)cu_count() * per_cu;
+    if (grid > P) grid = P;
+    kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap);
+    return hipGetLastError();
+}
+
+template <typename K, bool PAY>
+static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_t nkeys,
+                                 void* out_v, uint32_t* out_pay, int64_t nout,
+                                 const PieceDesc* desc, int64_t P, uint32_t cap, hipStream_t st) {
+    const K* keys = static_cast<const K*>(keys_v);
+    K* out = static_cast<K*>(out_v);
+    if (P <= 0) return hipSuccess;
+    if (fits_regs<K, PAY>(cap, 5))
+        return launch_persistent<K, PAY, 5>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap, st);
+    if (fits_regs<K, PAY>(cap, 9))
+        return launch_persistent<K, PAY, 9>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap, st);
+    constexpr int L = kMergeThreads;
+    auto kern = merge_direct_kernel<K, PAY, L>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = allow_big_lds(kern);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
+    kern<<<(unsigned)P, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
+                        const int64_t* ybar, PieceDesc* desc, hipStream_t st) {
+    const int64_t P = p_a + p_b;
+    cases_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(n, m, p_a, p_b, xbar, ybar, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
+                             void* out_keys, uint32_t* out_pay, int64_t nout,
+                             const PieceDesc* desc, int64_t P, uint32_t cap, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    with_dtype(dtype, [&](auto z) {
+        using K = decltype(z);
+        e = pay ? launch_merge_t<K, true>(keys, pay, nkeys, out_keys, out_pay, nout, desc, P, cap, st)
+                : launch_merge_t<K, false>(keys, nullptr, nkeys, out_keys, nullptr, nout, desc, P,
+                                           cap, st);
+    });
+    return e;
+}
+
+hipError_t launch_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n, int64_t m,
+                        int64_t p_a, int64_t p_b, const int64_t* xbar, const int64_t* ybar,
+                        PieceDesc* desc, void* out_keys, uint32_t* out_pay, uint32_t cap,
+                        hipStream_t st) {
+    hipError_t e = launch_cases(n, m, p_a, p_b, xbar, ybar, desc, st);
+    if (e != hipSuccess) return e;
+    return launch_merge_desc(dtype, keys, pay, n + m, out_keys, out_pay, n + m, desc, p_a + p_b,
+                             cap, st);
+}
+
+hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, int* flag,
+                           hipStream_t st) {
+    const int64_t total = n + m;
+    int64_t g = (total + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    with_dtype(dtype, [&](auto z) {
+        using K = decltype(z);
+        validate_kernel<K><<<(unsigned)g, 256, 0, st>>>(static_cast<const K*>(keys), n, m, flag);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace sm

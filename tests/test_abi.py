@@ -1,0 +1,84 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/stablemerge.h declares, and rejects bad arguments before launching
+anything (no GPU is touched: every call here fails host-side validation)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(HEADER_DIR, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for mt in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M):
+            if not mt.group(0).lstrip().startswith(("typedef", "#", "return")):
+                names.add(mt.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def sm():
+    import paper_1202_6575_amd as m
+    return m
+
+
+def test_exports_every_declared_symbol(sm):
+    lib = ctypes.CDLL(sm.LIB_PATH)
+    names = declared_functions()
+    assert {"stable_merge", "stable_merge_partition", "stable_merge_workspace_bytes",
+            "sm_last_error"} <= names
+    for name in sorted(names):
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+
+
+def call_merge(sm, keys=0x10000, pay=None, n=10, m=10, out=0x20000, opay=None, dtype=1,
+               ws=0x30000, ws_bytes=1 << 20, opts=None):
+    o = opts if opts is not None else sm.Options()
+    return sm._lib.stable_merge(keys, pay, n, m, out, opay, dtype, ws, ws_bytes,
+                                ctypes.byref(o), None)
+
+
+def test_error_paths(sm):
+    assert call_merge(sm, dtype=7) == -2
+    assert call_merge(sm, n=-1) == -1
+    assert call_merge(sm, pay=0x40000) == -1                      # payload without out_payloads
+    assert call_merge(sm, keys=None) == -1
+    assert call_merge(sm, keys=0x10004) == -1                     # not 16-byte aligned
+    assert call_merge(sm, out=0x10000 + 16) == -3                 # out overlaps keys
+    assert call_merge(sm, ws_bytes=8) == -4
+    assert call_merge(sm, ws=None) == -4
+    assert b"workspace" in sm._lib.sm_last_error()
+    o = sm.Options()
+    o.p_a = -3
+    assert call_merge(sm, opts=o) == -1
+    o = sm.Options()
+    o.p_a, o.p_b = 1, 1                                            # subproblem too big for LDS
+    assert call_merge(sm, n=1 << 22, m=1 << 22, opts=o) == -1
+    assert call_merge(sm, n=0, m=0) == 0                           # nothing to do
+
+
+def test_partition_error_paths(sm):
+    f = sm._lib.stable_merge_partition
+    assert f(0x10000, 10, 10, 0, 1, 1, 0x20000, 0x30000, None) == -1
+    assert f(0x10000, 10, 10, 1, 1, 9, 0x20000, 0x30000, None) == -2
+    assert f(0x10000, 10, 10, 1, 1, 1, None, 0x30000, None) == -1
+
+
+def test_workspace_bytes(sm):
+    import torch
+    w = sm.workspace_bytes(1 << 20, 1 << 19, torch.uint32)
+    assert w >= ((1 << 20) // 2048 + (1 << 19) // 2048 + 2) * 8
+    assert sm.workspace_bytes(-1, 3, torch.uint32) == 0
+    assert sm.workspace_bytes(100, 100, torch.uint32, p_a=5, p_b=5) == 256 + 256 + 10 * 32
+
+
+def test_version(sm):
+    assert sm._lib.sm_version() >= 100

@@ -1,0 +1,209 @@
+"""GPU parity of the plain stable merge against the CPU oracle (bit-exact).
+
+Every case runs the HIP path through the C ABI (paper_1202_6575_amd) and
+compares keys and payloads element by element with the oracle on the same
+seeded inputs.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from helpers import dev, flush, host, rand_sorted
+
+pytestmark = pytest.mark.gpu
+
+import paper_1202_6575_amd as sm  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "figure1.json")
+DTYPES = [np.int32, np.uint32, np.uint64]
+
+
+def run_merge(A, B, pa=None, pb=None, **kw):
+    keys = dev(np.concatenate([A, B]))
+    pay = None if pa is None else dev(np.concatenate([pa, pb]).astype(np.uint32))
+    ck, cp = sm.merge(keys, len(A), len(B), pay, **kw)
+    torch.cuda.synchronize()
+    return host(ck), (None if cp is None else host(cp))
+
+
+def check(A, B, with_pay=True, **kw):
+    n, m = len(A), len(B)
+    pa = pb = None
+    if with_pay:
+        pa, pb = datagen.source_tag_payloads(n, m)
+    rk, rp = oracle.merge(A, B, pa, pb)
+    ck, cp = run_merge(A, B, pa, pb, **kw)
+    assert np.array_equal(ck, rk), f"keys differ at {np.flatnonzero(ck != rk)[:10]}"
+    if with_pay:
+        assert np.array_equal(cp, rp), f"payloads differ at {np.flatnonzero(cp != rp)[:10]}"
+
+
+def test_figure1_partition_and_merge():
+    flush("figure1")
+    with open(GOLD) as f:
+        g = json.load(f)
+    A = np.array(g["A"], dtype=np.int32)
+    B = np.array(g["B"], dtype=np.int32)
+    xbar, ybar = sm.partition(dev(np.concatenate([A, B])), len(A), len(B), g["p"])
+    assert host(xbar).tolist() == g["xbar"]
+    assert host(ybar).tolist() == g["ybar"]
+    check(A, B, p_a=5, p_b=5)
+    check(A, B)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_partition_matches_oracle(dtype):
+    g = np.random.default_rng(21)
+    for trial in range(20):
+        n, m = int(g.integers(0, 5000)), int(g.integers(0, 5000))
+        p_a, p_b = int(g.integers(1, 300)), int(g.integers(1, 300))
+        A, B = rand_sorted(g, n, int(g.integers(1, 500)), dtype), rand_sorted(g, m, 300, dtype)
+        flush(f"partition dtype={np.dtype(dtype).name} n={n} m={m} p_a={p_a} p_b={p_b}")
+        xb, yb = sm.partition(dev(np.concatenate([A, B])), n, m, p_a, p_b)
+        rx, ry = oracle.cross_ranks(A, B, p_a, p_b)
+        assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
+
+
+def test_config1_partition_p256():
+    """The config-1 arrays (int32 uniform in [0, 65536), n = 1e6, m = 6e5), p = 256."""
+    A, B = datagen.uniform_pair(1_000_000, 600_000, 0, 65536, np.int32, seed=datagen.BASE_SEED)
+    flush("config1 partition p=256")
+    xb, yb = sm.partition(dev(np.concatenate([A, B])), len(A), len(B), 256)
+    rx, ry = oracle.cross_ranks(A, B, 256)
+    assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
+
+
+def test_config1_merge_p256():
+    A, B = datagen.uniform_pair(1_000_000, 600_000, 0, 65536, np.int32, seed=datagen.BASE_SEED)
+    flush("config1 merge p=256 and auto")
+    check(A, B, p_a=256, p_b=256)
+    check(A, B)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_random_small(dtype, with_pay):
+    g = np.random.default_rng(1000 + DTYPES.index(dtype) + 10 * with_pay)
+    for trial in range(25):
+        n, m = int(g.integers(0, 3000)), int(g.integers(0, 3000))
+        alpha = int(g.integers(1, 2000))
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        tile = int(g.choice([1, 2, 7, 64, 300, 2048]))
+        flush(f"small dtype={np.dtype(dtype).name} pay={with_pay} n={n} m={m} tile={tile}")
+        check(A, B, with_pay, tile=tile)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_several_tiles_ragged(dtype, with_pay):
+    """Sizes spanning many top-level blocks with ragged ends."""
+    g = np.random.default_rng(77)
+    for n, m, alpha in [(100_003, 77_777, 1 << 30), (65_537, 1, 10), (1, 65_537, 10),
+                        (250_001, 249_999, 50), (3, 200_000, 5)]:
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        flush(f"tiles dtype={np.dtype(dtype).name} pay={with_pay} n={n} m={m}")
+        check(A, B, with_pay)
+
+
+@pytest.mark.parametrize("p", [2, 5, 17, 256])
+def test_forced_p(p):
+    g = np.random.default_rng(p)
+    A, B = rand_sorted(g, 20_000, 100, np.uint32), rand_sorted(g, 9_000, 100, np.uint32)
+    flush(f"forced p={p}")
+    check(A, B, True, p_a=p, p_b=p)
+    check(A, B, False, p_a=p, p_b=max(1, p // 2))
+
+
+def test_tiling_independence():
+    """A stable merge is unique: every tiling gives the same bytes."""
+    g = np.random.default_rng(3)
+    A, B = rand_sorted(g, 50_000, 64, np.int32), rand_sorted(g, 30_000, 64, np.int32)
+    pa, pb = datagen.source_tag_payloads(len(A), len(B))
+    ref = run_merge(A, B, pa, pb)
+    for kw in [dict(tile=1), dict(tile=16), dict(tile=1000), dict(p_a=3, p_b=7),
+               dict(p_a=1000, p_b=1)]:
+        flush(f"tiling {kw}")
+        got = run_merge(A, B, pa, pb, **kw)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_special_cases(dtype):
+    z = np.zeros(0, dtype=dtype)
+    k = lambda *v: np.array(v, dtype=dtype)
+    ar = lambda lo, hi, st=1: np.arange(lo, hi, st).astype(dtype)
+    cases = [(z, z), (ar(0, 10), z), (z, ar(0, 10)), (k(5, 5, 5, 5), k(5, 5, 5)),
+             (ar(0, 5000), ar(4999, 9000)), (ar(5000, 9000), ar(0, 5000)),
+             (ar(0, 20000, 2), ar(1, 20001, 2)), (k(3), k(3)),
+             (np.full(10000, 7, dtype), np.full(9000, 7, dtype))]
+    for A, B in cases:
+        flush(f"special dtype={np.dtype(dtype).name} n={len(A)} m={len(B)}")
+        check(A, B, True)
+        check(A, B, False)
+        check(A, B, True, tile=1)
+
+
+def test_validate_detects_unsorted():
+    A = np.array([1, 2, 3, 2], dtype=np.uint32)
+    B = np.array([1, 5], dtype=np.uint32)
+    with pytest.raises(sm.SMError) as e:
+        sm.merge(dev(np.concatenate([A, B])), 4, 2, validate=True)
+    assert e.value.code == -6
+    check(np.sort(A), B, True, validate=True)
+
+
+def test_alias_rejected():
+    keys = dev(np.arange(10, dtype=np.uint32))
+    with pytest.raises(sm.SMError) as e:
+        sm.merge(keys, 5, 5, out_keys=keys)
+    assert e.value.code == -3
+
+
+def test_unaligned_view():
+    """A view that starts 1 element into a buffer is rejected, not misread."""
+    keys = dev(np.arange(11, dtype=np.uint32))[1:]
+    with pytest.raises(sm.SMError) as e:
+        sm.merge(keys, 5, 5)
+    assert e.value.code == -1
+
+
+@pytest.mark.slow
+def test_config2_full_size():
+    """n = m = 2^28 uint32 uniform over the full range, keys only: the whole
+    output against the oracle, in the default launch configuration."""
+    n = m = 1 << 28
+    flush("config2 generate")
+    A, B = datagen.uniform_pair(n, m, 0, 2 ** 32, np.uint32, seed=datagen.BASE_SEED + 1)
+    keys = dev(np.concatenate([A, B]))
+    flush("config2 gpu merge")
+    ck, _ = sm.merge(keys, n, m)
+    torch.cuda.synchronize()
+    got = host(ck)
+    del keys, ck
+    flush("config2 oracle merge")
+    ref, _ = oracle.merge(A, B)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.slow
+def test_config3_full_size():
+    """n = 2^27, m = 2^23 uint64 Zipf(1.1) keys, payload = concatenated index."""
+    n, m = 1 << 27, 1 << 23
+    flush("config3 generate")
+    A, B = datagen.zipf_pair(n, m, 1.1, 10 ** 6, seed=datagen.BASE_SEED + 2)
+    pa, pb = datagen.index_payloads(n, m)
+    keys = dev(np.concatenate([A, B]))
+    pay = dev(np.concatenate([pa, pb]))
+    flush("config3 gpu merge")
+    ck, cp = sm.merge(keys, n, m, pay)
+    torch.cuda.synchronize()
+    gk, gp = host(ck), host(cp)
+    del keys, pay, ck, cp
+    flush("config3 oracle merge")
+    rk, rp = oracle.merge(A, B, pa, pb)
+    assert np.array_equal(gk, rk) and np.array_equal(gp, rp)

@@ -431,3 +431,37 @@ def test_config1_shape_small():
     assert np.array_equal(c, ak) and np.array_equal(pc, ap)
     c, pc = oracle.merge_by_pieces(A, B, 256, 256, pa, pb)
     assert np.array_equal(c, ak) and np.array_equal(pc, ap)
+
+
+def successor_property(A, B, pcs):
+    """For each subproblem: the element after its A range is strictly greater
+    than every element of its B range, and the element after its B range is
+    greater than or equal to every element of its A range (when they exist).
+    The GPU merge loop relies on this to run without bounds checks."""
+    n, m = len(A), len(B)
+    for alo, ahi, blo, bhi, _, _ in pcs:
+        if ahi < n and bhi > blo:
+            assert A[ahi] > B[blo:bhi].max()
+        if bhi < m and ahi > alo:
+            assert B[bhi] >= A[alo:ahi].max()
+
+
+def test_successor_sentinels_exhaustive():
+    seqs = [s for L in range(0, 5) for s in nondecreasing(L, 3)]
+    for A in seqs:
+        for B in seqs:
+            for p_a in range(1, 6):
+                for p_b in range(1, 6):
+                    xbar, ybar = oracle.cross_ranks(A, B, p_a, p_b)
+                    successor_property(A, B, oracle.pieces(len(A), len(B), p_a, p_b, xbar, ybar))
+
+
+def test_successor_sentinels_random():
+    g = np.random.default_rng(31)
+    for _ in range(2000):
+        n, m = int(g.integers(0, 80)), int(g.integers(0, 80))
+        alpha = int(g.integers(1, 40))
+        A, B = rand_sorted(g, n, alpha, np.int32), rand_sorted(g, m, alpha, np.int32)
+        p_a, p_b = int(g.integers(1, 20)), int(g.integers(1, 20))
+        xbar, ybar = oracle.cross_ranks(A, B, p_a, p_b)
+        successor_property(A, B, oracle.pieces(n, m, p_a, p_b, xbar, ybar))
