@@ -38,7 +38,8 @@ struct Blocks {
 };
 
 // Quotient k / d for 0 <= k < 2^22 and a workgroup-uniform divisor d >= 1
-// with rd = 1 / d: a float product, then one exact correction step.
+// with rd ~ 1 / d (hardware reciprocal, within an ulp): the float product is
+// within one of the quotient, and one exact correction step fixes it.
 __device__ __forceinline__ int fast_div(int k, int d, float rd) {
     int q = (int)((float)k * rd);
     const int r = k - q * d;
@@ -58,8 +59,8 @@ struct LaneBlocks {
         r = len - q * L;
         c = q + (r != 0);
         rc = r * c;
-        rcp_c = c > 0 ? 1.0f / (float)c : 0.0f;
-        rcp_q = q > 0 ? 1.0f / (float)q : 0.0f;
+        rcp_c = c > 0 ? __builtin_amdgcn_rcpf((float)c) : 0.0f;
+        rcp_q = q > 0 ? __builtin_amdgcn_rcpf((float)q) : 0.0f;
     }
     __device__ int start(int i) const {
         if (i >= L) return len;
@@ -221,6 +222,31 @@ __device__ __forceinline__ int lower_bound_lds(const K* X, int n, K x) {
     return base + (X[base] < x ? 1 : 0);
 }
 
+// Both lane-level searches at once: lower_bound of x in X[0, nx) and
+// upper_bound of y in Y[0, ny).  The two probe chains are independent, so
+// each step issues both reads before waiting: half the dependent LDS round
+// trips of running them one after the other.
+template <typename K, int STEPS>
+__device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const K* Y, int ny, K y,
+                                                  int& rx, int& ry) {
+    int bx = 0, by = 0;
+    int lx = nx, ly = ny;
+    // STEPS >= ceil(log2(max(nx, ny))); once a length reaches 1 its half is
+    // 0 and the step re-reads the same slot without moving
+#pragma unroll
+    for (int i = 0; i < STEPS; ++i) {
+        const int hx = lx >> 1, hy = ly >> 1;
+        const K vx = X[bx + hx];
+        const K vy = Y[by + hy];
+        bx = vx < x ? bx + hx : bx;
+        by = !(y < vy) ? by + hy : by;
+        lx -= hx;
+        ly -= hy;
+    }
+    rx = nx > 0 ? bx + (X[bx] < x ? 1 : 0) : 0;
+    ry = ny > 0 ? by + (!(y < Y[by]) ? 1 : 0) : 0;
+}
+
 template <typename K>
 __device__ __forceinline__ int upper_bound_lds(const K* X, int n, K x) {
     if (n <= 0) return 0;
@@ -231,6 +257,18 @@ __device__ __forceinline__ int upper_bound_lds(const K* X, int n, K x) {
         len -= half;
     }
     return base + (!(x < X[base]) ? 1 : 0);
+}
+
+template <typename K>
+__device__ __forceinline__ void paired_bounds_any(const K* X, int nx, K x, const K* Y, int ny, K y,
+                                                  int& rx, int& ry) {
+    const int n = nx > ny ? nx : ny;
+    if (n <= 4096) {
+        paired_bounds_lds<K, 12>(X, nx, x, Y, ny, y, rx, ry);
+    } else {
+        rx = lower_bound_lds<K>(X, nx, x);
+        ry = upper_bound_lds<K>(Y, ny, y);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -386,14 +424,14 @@ __device__ __forceinline__ void prefetch(const SegPlan& p, const K* keys, uint64
                            (p.kb_al + p.offB - p.offPB) * 4, p.ncpb, rp);
 }
 
-// Key chunk q after the successor fix-up: a successor slot whose segment
-// ends its source array holds the key type's maximum.
-template <typename K>
-__device__ __forceinline__ u32x4 fix_successor(const SegPlan& p, int q, u32x4 v) {
-    K* e = reinterpret_cast<K*>(&v);
-    if (q == p.qsA && !p.succA) e[p.esA] = KeyMax<K>::v;
-    if (q == p.qsB && !p.succB) e[p.esB] = KeyMax<K>::v;
-    return v;
+// A successor slot whose segment ends its source array must hold the key
+// type's maximum.  The lane that wrote the chunk holding the slot overwrites
+// it after its own chunk write, so no other lane races on it.
+template <typename K, int L>
+__device__ __forceinline__ void fix_successors(const SegPlan& p, K* sKey) {
+    const int t = threadIdx.x;
+    if (!p.succA && t == p.qsA % L) sKey[p.offA + p.a] = KeyMax<K>::v;
+    if (!p.succB && t == p.qsB % L) sKey[p.wa + p.offB + p.b] = KeyMax<K>::v;
 }
 
 template <typename K, bool PAY, int L, int R>
@@ -408,11 +446,10 @@ __device__ __forceinline__ void commit(const SegPlan& p, const u32x4 (&rk)[R],
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int q = r * L + t;
-        if (q < p.nca + p.ncb) {
-            const u32x4 v = fix_successor<K>(p, q, rk[r]);
-            *reinterpret_cast<u32x4*>(sKey + (q < p.nca ? q * V : p.wa + (q - p.nca) * V)) = v;
-        }
+        if (q < p.nca + p.ncb)
+            *reinterpret_cast<u32x4*>(sKey + (q < p.nca ? q * V : p.wa + (q - p.nca) * V)) = rk[r];
     }
+    fix_successors<K, L>(p, sKey);
     if (PAY) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -433,11 +470,15 @@ __device__ __forceinline__ void stage_direct(const SegPlan& p, const K* keys, ui
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(keys + p.ka_al, (nkeys - p.ka_al) * sizeof(K));
     const __amdgpu_buffer_rsrc_t rB = make_rsrc(keys + p.kb_al, (nkeys - p.kb_al) * sizeof(K));
     for (int q = t; q < p.nca + p.ncb; q += L) {
-        if (q < p.nca)
-            *reinterpret_cast<u32x4*>(sKey + q * V) = fix_successor<K>(p, q, buf_load16(rA, q * 16));
-        else
-            *reinterpret_cast<u32x4*>(sKey + p.wa + (q - p.nca) * V) =
-                fix_successor<K>(p, q, buf_load16(rB, (q - p.nca) * 16));
+        if (q < p.nca) *reinterpret_cast<u32x4*>(sKey + q * V) = buf_load16(rA, q * 16);
+        else *reinterpret_cast<u32x4*>(sKey + p.wa + (q - p.nca) * V) = buf_load16(rB, (q - p.nca) * 16);
+    }
+    // the successor slots belong to chunks this lane may not have written:
+    // order the patch after every chunk write
+    __syncthreads();
+    if (t == 0) {
+        if (!p.succA) sKey[p.offA + p.a] = KeyMax<K>::v;
+        if (!p.succB) sKey[p.wa + p.offB + p.b] = KeyMax<K>::v;
     }
     if (PAY) {
         const __amdgpu_buffer_rsrc_t qA = make_rsrc(pay + (p.ka_al + p.offA - p.offPA),
@@ -484,6 +525,45 @@ __device__ __forceinline__ void lane_merge_uniform(const K* sKey, K* sOut, uint3
     } while (__any(k < len));
 }
 
+// Two lane subproblems merged in one loop: the two chains of dependent LDS
+// reads are independent, so each step waits once for both.  Same uniform
+// trip-count rule as lane_merge_uniform (the larger of the two lengths,
+// maximised over the wave).
+template <typename K, bool PAY>
+__device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint32_t* sIdx,
+                                                    int ia1, int ib1, int len1, int co1, int cp1,
+                                                    int ia2, int ib2, int len2, int co2, int cp2) {
+    const int len = len1 > len2 ? len1 : len2;
+    if (!__any(len > 0)) return;
+    K ka1 = sKey[ia1], kb1 = sKey[ib1];
+    K ka2 = sKey[ia2], kb2 = sKey[ib2];
+    int k = 0;
+    do {
+        const bool t1 = kb1 < ka1;
+        const bool t2 = kb2 < ka2;
+        const int s1 = t1 ? ib1 : ia1;
+        const int s2 = t2 ? ib2 : ia2;
+        sOut[co1 + k] = t1 ? kb1 : ka1;
+        sOut[co2 + k] = t2 ? kb2 : ka2;
+        if (PAY) {
+            sIdx[cp1 + k] = (uint32_t)s1;
+            sIdx[cp2 + k] = (uint32_t)s2;
+        }
+        const int n1 = s1 + 1, n2 = s2 + 1;
+        const K kn1 = sKey[n1];
+        const K kn2 = sKey[n2];
+        ib1 = t1 ? n1 : ib1;
+        ia1 = t1 ? ia1 : n1;
+        kb1 = t1 ? kn1 : kb1;
+        ka1 = t1 ? ka1 : kn1;
+        ib2 = t2 ? n2 : ib2;
+        ia2 = t2 ? ia2 : n2;
+        kb2 = t2 ? kn2 : kb2;
+        ka2 = t2 ? ka2 : kn2;
+        ++k;
+    } while (__any(k < len));
+}
+
 // Bounds-checked form: each lane stops after its own la + lb outputs.
 template <typename K, bool PAY>
 __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint32_t* sIdx, int ia,
@@ -518,10 +598,14 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
     const LaneBlocks<L> LA(a), LB(b);
     {
-        const int xt = LA.start(t);
-        sXb[t] = xt < a ? lower_bound_lds<K>(sKey + baseB, b, sKey[baseA + xt]) : b;
-        const int yt = LB.start(t);
-        sYb[t] = yt < b ? upper_bound_lds<K>(sKey + baseA, a, sKey[baseB + yt]) : a;
+        const int xt = LA.start(t), yt = LB.start(t);
+        // lanes without a block start search with the successor slot's key
+        // and discard the result
+        int rx, ry;
+        paired_bounds_any<K>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
+                             sKey[baseB + (yt < b ? yt : b)], rx, ry);
+        sXb[t] = xt < a ? rx : b;
+        sYb[t] = yt < b ? ry : a;
         if (t == 0) {
             sXb[L] = b;
             sYb[L] = a;
@@ -534,21 +618,31 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const bool fast = p.succA || b == 0 || sKey[baseB + b - 1] != KeyMax<K>::v;
 
     // ---- per-lane stable sequential merges (Steps 3-4 inside the WG) ------
-#pragma unroll 1
+    // lane t is the processing element of A block t (Step 3) and of B block
+    // t (Step 4); a descriptor outside the segment would be a bug and merges
+    // nothing
+    Piece<int> pc[2] = {step3_piece<int>(LA, LB, sXb, sYb, t), step4_piece<int>(LA, LB, sXb, sYb, t)};
+    int la[2], lb[2];
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
-        const Piece<int> pc = side == 0 ? step3_piece<int>(LA, LB, sXb, sYb, t)
-                                        : step4_piece<int>(LA, LB, sXb, sYb, t);
-        // a descriptor outside the segment would be a bug; it merges nothing
-        const bool ok = 0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= a && 0 <= pc.b_lo &&
-                        pc.b_lo <= pc.b_hi && pc.b_hi <= b && 0 <= pc.c_off &&
-                        pc.c_off + (pc.a_hi - pc.a_lo) + (pc.b_hi - pc.b_lo) <= s;
-        const int la = ok ? pc.a_hi - pc.a_lo : 0, lb = ok ? pc.b_hi - pc.b_lo : 0;
-        if (fast)
-            lane_merge_uniform<K, PAY>(sKey, sOut, sIdx, baseA + pc.a_lo, baseB + pc.b_lo, la + lb,
-                                       p.offC + pc.c_off, p.offCP + pc.c_off);
-        else
-            lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + pc.a_lo, la, baseB + pc.b_lo, lb,
-                                       p.offC + pc.c_off, p.offCP + pc.c_off);
+        const Piece<int>& q = pc[side];
+        const bool ok = 0 <= q.a_lo && q.a_lo <= q.a_hi && q.a_hi <= a && 0 <= q.b_lo &&
+                        q.b_lo <= q.b_hi && q.b_hi <= b && 0 <= q.c_off &&
+                        q.c_off + (q.a_hi - q.a_lo) + (q.b_hi - q.b_lo) <= s;
+        la[side] = ok ? q.a_hi - q.a_lo : 0;
+        lb[side] = ok ? q.b_hi - q.b_lo : 0;
+    }
+    if (fast) {
+        lane_merge_uniform2<K, PAY>(sKey, sOut, sIdx, baseA + pc[0].a_lo, baseB + pc[0].b_lo,
+                                    la[0] + lb[0], p.offC + pc[0].c_off, p.offCP + pc[0].c_off,
+                                    baseA + pc[1].a_lo, baseB + pc[1].b_lo, la[1] + lb[1],
+                                    p.offC + pc[1].c_off, p.offCP + pc[1].c_off);
+    } else {
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side)
+            lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + pc[side].a_lo, la[side],
+                                       baseB + pc[side].b_lo, lb[side], p.offC + pc[side].c_off,
+                                       p.offCP + pc[side].c_off);
     }
     __syncthreads();
 
@@ -568,61 +662,46 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
 // element stores at the two partial ends.  Reads only sOut / sIdx, so it
 // may run after the staging buffers have been refilled.  RW = number of
 // output chunks per thread, unrolled (0 = a loop, for large subproblems).
-template <typename K, bool PAY, int L, int RW>
-__device__ __forceinline__ void write_back(const SegPlan& p, const K* sOut, const uint32_t* sIdx,
-                                           K* out, uint32_t* out_pay) {
-    constexpr int V = Vec<K>::N;
+template <typename E, int L, int RW>
+__device__ __forceinline__ void write_out(const E* sArr, int off, int s, E* base_out) {
+    // base_out = output position of sArr[0]; elements [off, off + s) are real;
+    // chunks of V = 16 / sizeof(E) elements aligned to base_out
+    constexpr int V = 16 / sizeof(E);
     const int t = threadIdx.x;
-    const int s = p.s;
-    if (s == 0) return;
-    K* baseC = out + (p.c0 - p.offC);
-    const int ncc = (p.offC + s + V - 1) / V;
-    auto key_chunk = [&](int q) {
-        const int lo = q * V;
-        if (lo >= p.offC && lo + V <= p.offC + s) {
-            *reinterpret_cast<u32x4*>(baseC + lo) = *reinterpret_cast<const u32x4*>(sOut + lo);
-        } else {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const int k = lo + e;
-                if (k >= p.offC && k < p.offC + s) baseC[k] = sOut[k];
-            }
-        }
+    const int q0 = (off + V - 1) / V, q1 = (off + s) / V;   // full chunks [q0, q1)
+    auto chunk = [&](int q) {
+        *reinterpret_cast<u32x4*>(base_out + q * V) = *reinterpret_cast<const u32x4*>(sArr + q * V);
     };
     if (RW > 0) {
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            const int q = r * L + t;
-            if (q < ncc) key_chunk(q);
+            const int q = q0 + r * L + t;
+            if (q < q1) chunk(q);
         }
     } else {
-        for (int q = t; q < ncc; q += L) key_chunk(q);
+        for (int q = q0 + t; q < q1; q += L) chunk(q);
     }
-    if (PAY) {
-        uint32_t* baseP = out_pay + (p.c0 - p.offCP);
-        const int ncp = (p.offCP + s + 3) / 4;
-        auto pay_chunk = [&](int q) {
-            const int lo = q * 4;
-            if (lo >= p.offCP && lo + 4 <= p.offCP + s) {
-                *reinterpret_cast<u32x4*>(baseP + lo) = *reinterpret_cast<const u32x4*>(sIdx + lo);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = lo + e;
-                    if (k >= p.offCP && k < p.offCP + s) baseP[k] = sIdx[k];
-                }
-            }
-        };
-        if (RW > 0) {
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const int q = r * L + t;
-                if (q < ncp) pay_chunk(q);
-            }
-        } else {
-            for (int q = t; q < ncp; q += L) pay_chunk(q);
-        }
+    // the elements outside the full chunks: at most V - 1 at each end
+    if (t < 2 * V) {
+        int k;
+        if (q1 < q0) k = t < V ? off + t : off + s;   // no full chunk: head covers all
+        else k = t < V ? off + t : q1 * V + (t - V);
+        const bool head = t < V && k < (q1 < q0 ? off + s : q0 * V);
+        const bool tail = t >= V && q1 >= q0 && k < off + s;
+        if (head || tail) base_out[k] = sArr[k];
     }
+}
+
+// Write-back of merged outputs: aligned 16-byte stores for whole chunks,
+// element stores at the two partial ends.  Reads only sOut / sIdx, so it
+// may run after the staging buffers have been refilled.  RW = number of
+// output chunks per thread, unrolled (0 = a loop, for large subproblems).
+template <typename K, bool PAY, int L, int RW>
+__device__ __forceinline__ void write_back(const SegPlan& p, const K* sOut, const uint32_t* sIdx,
+                                           K* out, uint32_t* out_pay) {
+    if (p.s == 0) return;
+    write_out<K, L, RW>(sOut, p.offC, p.s, out + (p.c0 - p.offC));
+    if (PAY) write_out<uint32_t, L, RW>(sIdx, p.offCP, p.s, out_pay + (p.c0 - p.offCP));
 }
 
 // LDS carve-up shared by the merge kernels.
