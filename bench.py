@@ -15,6 +15,16 @@ algorithmic bytes per launch = (n + m) * 2 * (key bytes + payload bytes)
 duration from HIP events recorded on the launch stream around it.
 ``cpu_baseline`` times the CPU oracle's sequential two-pointer merge on the
 same arrays (one host thread).
+
+``copy_reference`` is a plain elementwise stream over the same bytes
+(bitwise NOT of the keys as int32: read 4 B, write 4 B per element), timed
+the same way; it is the achievable-bandwidth context for the roofline, and
+its rocprofv3 counters calibrate the merge kernel's FETCH_SIZE / WRITE_SIZE.
+
+``python bench.py --summarize-pmc FETCH_DIR WRITE_DIR`` reads two
+``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` output directories of
+this benchmark (csv format) and writes the per-launch HBM traffic of the
+merge kernel, scaled by the copy kernel's counters, to the profiles folder.
 """
 from __future__ import annotations
 
@@ -57,6 +67,51 @@ def traffic_from_profile(launch_bytes_alg: float):
     return pmc.get("hbm_bytes_per_launch")
 
 
+MERGE_KERNEL_TAG = "merge_persistent_kernel"
+COPY_KERNEL_TAG = "bitwise_not"
+
+
+def _pmc_per_dispatch(run_dir: str, counter: str):
+    """Mean counter value per dispatch for the merge and the copy kernel."""
+    import csv
+    import glob
+    vals = {"merge": [], "copy": []}
+    for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = "merge" if MERGE_KERNEL_TAG in name else ("copy" if COPY_KERNEL_TAG in name else None)
+            if key:
+                vals[key].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v) if v else None) for k, v in vals.items()}
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, log2n: int, out_path: str = PMC_FILE):
+    n = m = 1 << log2n
+    stream_bytes = (n + m) * 4           # the copy reads this many bytes and writes as many
+    f = _pmc_per_dispatch(fetch_dir, "FETCH_SIZE")
+    w = _pmc_per_dispatch(write_dir, "WRITE_SIZE")
+    if None in (f["merge"], f["copy"], w["merge"], w["copy"]):
+        raise SystemExit(f"missing counters: fetch={f} write={w}")
+    # counters are in KiB per dispatch; scale each by what it reads for the copy
+    sf = stream_bytes / (f["copy"] * 1024.0)
+    sw = stream_bytes / (w["copy"] * 1024.0)
+    fetch_b = f["merge"] * 1024.0 * sf
+    write_b = w["merge"] * 1024.0 * sw
+    out = {"kernel": "merge_persistent_kernel<uint32, keys only>",
+           "workload": f"n=m=2^{log2n} uint32 uniform, keys only",
+           "source_hash": kernel_source_hash(),
+           "fetch_kib_per_dispatch": f["merge"], "write_kib_per_dispatch": w["merge"],
+           "copy_fetch_kib_per_dispatch": f["copy"], "copy_write_kib_per_dispatch": w["copy"],
+           "copy_stream_bytes": stream_bytes, "fetch_scale": sf, "write_scale": sw,
+           "hbm_bytes_per_launch": fetch_b + write_b,
+           "algorithmic_bytes_per_launch": (n + m) * 2 * 4}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,7 +121,12 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare one output with the oracle")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--pmc-out", default=PMC_FILE)
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.log2n, args.pmc_out)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -106,6 +166,18 @@ def main():
                         stream=stream)
         if ev is not None:
             ev[2].record(stream)
+
+    log("bench: copy reference")
+    src32, dst32 = keys.view(torch.int32), out.view(torch.int32)
+    torch.bitwise_not(src32, out=dst32)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(3):
+        torch.bitwise_not(src32, out=dst32)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 3
 
     log("bench: warmup")
     for _ in range(args.warmup):
@@ -172,6 +244,9 @@ def main():
                      "kernel": "merge_kernel<uint32, keys only>",
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
+        "copy_reference": {"GB/s": round(alg_bytes / (copy_ms * 1e-3) / 1e9, 1),
+                           "ms": round(copy_ms, 4),
+                           "kernel": "elementwise bitwise_not, reads and writes n+m uint32"},
     }
     print(json.dumps(res), flush=True)
 

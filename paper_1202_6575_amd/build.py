@@ -45,5 +45,34 @@ def build_library(verbose: bool = False) -> str:
     return LIB
 
 
+def kernel_resources(src_name: str = "sm_merge.hip"):
+    """Compile one source with hipcc's resource-usage remarks and return
+    {kernel: {"vgprs": int, "scratch": int, "occupancy": int}}."""
+    import re
+    import tempfile
+    src = os.path.join(HERE, "csrc", src_name)
+    with tempfile.TemporaryDirectory() as td:
+        cmd = (["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "--cuda-device-only",
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-Rpass-analysis=kernel-resource-usage", "-I", os.path.join(ROOT, "include"),
+                "-c", src, "-o", os.path.join(td, "k.o")])
+        res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(res.stderr)
+    out, cur = {}, None
+    for line in res.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            out[cur] = {}
+            continue
+        for key, pat in (("vgprs", r"\bVGPRs: (\d+)"), ("scratch", r"ScratchSize \[bytes/lane\]: (\d+)"),
+                         ("occupancy", r"Occupancy \[waves/SIMD\]: (\d+)")):
+            m = re.search(pat, line)
+            if m and cur:
+                out[cur][key] = int(m.group(1))
+    return out
+
+
 if __name__ == "__main__":
     build_library(verbose=True)

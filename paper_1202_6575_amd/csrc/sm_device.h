@@ -621,28 +621,27 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     // lane t is the processing element of A block t (Step 3) and of B block
     // t (Step 4); a descriptor outside the segment would be a bug and merges
     // nothing
-    Piece<int> pc[2] = {step3_piece<int>(LA, LB, sXb, sYb, t), step4_piece<int>(LA, LB, sXb, sYb, t)};
-    int la[2], lb[2];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        const Piece<int>& q = pc[side];
-        const bool ok = 0 <= q.a_lo && q.a_lo <= q.a_hi && q.a_hi <= a && 0 <= q.b_lo &&
-                        q.b_lo <= q.b_hi && q.b_hi <= b && 0 <= q.c_off &&
-                        q.c_off + (q.a_hi - q.a_lo) + (q.b_hi - q.b_lo) <= s;
-        la[side] = ok ? q.a_hi - q.a_lo : 0;
-        lb[side] = ok ? q.b_hi - q.b_lo : 0;
-    }
+    // (no arrays indexed by a loop variable here: they would live in scratch
+    // memory, i.e. extra HBM traffic)
+    const Piece<int> p3 = step3_piece<int>(LA, LB, sXb, sYb, t);
+    const Piece<int> p4 = step4_piece<int>(LA, LB, sXb, sYb, t);
+    auto valid = [&](const Piece<int>& q) {
+        return 0 <= q.a_lo && q.a_lo <= q.a_hi && q.a_hi <= a && 0 <= q.b_lo && q.b_lo <= q.b_hi &&
+               q.b_hi <= b && 0 <= q.c_off && q.c_off + (q.a_hi - q.a_lo) + (q.b_hi - q.b_lo) <= s;
+    };
+    const bool ok3 = valid(p3), ok4 = valid(p4);
+    const int la3 = ok3 ? p3.a_hi - p3.a_lo : 0, lb3 = ok3 ? p3.b_hi - p3.b_lo : 0;
+    const int la4 = ok4 ? p4.a_hi - p4.a_lo : 0, lb4 = ok4 ? p4.b_hi - p4.b_lo : 0;
     if (fast) {
-        lane_merge_uniform2<K, PAY>(sKey, sOut, sIdx, baseA + pc[0].a_lo, baseB + pc[0].b_lo,
-                                    la[0] + lb[0], p.offC + pc[0].c_off, p.offCP + pc[0].c_off,
-                                    baseA + pc[1].a_lo, baseB + pc[1].b_lo, la[1] + lb[1],
-                                    p.offC + pc[1].c_off, p.offCP + pc[1].c_off);
+        lane_merge_uniform2<K, PAY>(sKey, sOut, sIdx, baseA + p3.a_lo, baseB + p3.b_lo, la3 + lb3,
+                                    p.offC + p3.c_off, p.offCP + p3.c_off, baseA + p4.a_lo,
+                                    baseB + p4.b_lo, la4 + lb4, p.offC + p4.c_off,
+                                    p.offCP + p4.c_off);
     } else {
-#pragma unroll 1
-        for (int side = 0; side < 2; ++side)
-            lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + pc[side].a_lo, la[side],
-                                       baseB + pc[side].b_lo, lb[side], p.offC + pc[side].c_off,
-                                       p.offCP + pc[side].c_off);
+        lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + p3.a_lo, la3, baseB + p3.b_lo, lb3,
+                                   p.offC + p3.c_off, p.offCP + p3.c_off);
+        lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + p4.a_lo, la4, baseB + p4.b_lo, lb4,
+                                   p.offC + p4.c_off, p.offCP + p4.c_off);
     }
     __syncthreads();
 
