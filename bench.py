@@ -152,7 +152,7 @@ def main():
     p_b = (m + tile - 1) // tile
     xbar = torch.empty(p_a + 1, dtype=torch.int64, device=dev)
     ybar = torch.empty(p_b + 1, dtype=torch.int64, device=dev)
-    ws = torch.empty(int(sm._lib.stable_merge_pieces_workspace_bytes(p_a, p_b)), dtype=torch.uint8,
+    ws = torch.empty(sm.pieces_workspace_bytes(n, m, p_a, p_b, torch.uint32), dtype=torch.uint8,
                      device=dev)
     stream = torch.cuda.current_stream()
 

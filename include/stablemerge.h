@@ -65,7 +65,10 @@ typedef enum {
  *  p_a, p_b   number of blocks of A and of B (Section 2, block decomposition).
  *             0 = ceil(len / tile).  Forcing them reproduces the paper's
  *             partition for a given p; the two may differ.
- *  tile       block length in elements when p_a / p_b are 0.
+ *  tile       block length in elements when p_a / p_b are 0 (1..65536; a
+ *             subproblem of up to 2 * tile elements must fit one
+ *             workgroup's LDS, else SM_ERR_ARG).  Forced p_a / p_b whose
+ *             subproblems exceed 2 * tile are split again with this tile.
  *  validate   nonzero: first check that A and B are non-decreasing (one extra
  *             read of the keys and a synchronisation with the host).
  */
@@ -86,8 +89,10 @@ SM_API int sm_version(void);
 /*
  * Bytes of device workspace stable_merge needs for these arguments: the two
  * cross-rank arrays of p_a + 1 and p_b + 1 int64 entries (Section 2, the
- * synchronisation remark), a status word, and one 32-byte descriptor per
- * subproblem.  Returns 0 on bad arguments.
+ * synchronisation remark), a status word, one 32-byte descriptor per
+ * subproblem and, when forced block counts make subproblems larger than one
+ * workgroup stages, the state of their second-level split.  Returns 0 on
+ * bad arguments.
  */
 SM_API size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
                                     const sm_options *opt);
@@ -125,11 +130,12 @@ SM_API int stable_merge_partition(const void *keys, int64_t n, int64_t m, int64_
  * (a)-(e) and merges its subproblem into out_keys (and out_payloads).
  * stable_merge_partition followed by this call on one stream is exactly
  * stable_merge with forced p_a, p_b; the stream order is the method's single
- * synchronisation.  Requires ceil(n/p_a) + ceil(m/p_b) to fit one
- * workgroup (SM_ERR_ARG otherwise).  Same aliasing, alignment and payload
- * rules as stable_merge.  ws (device, 16-byte aligned) receives the p_a + p_b
- * subproblem descriptors and must hold stable_merge_pieces_workspace_bytes()
- * bytes (SM_ERR_WORKSPACE otherwise).
+ * synchronisation.  Subproblems larger than one workgroup stages (few
+ * blocks) are split again by the same method.  Same aliasing, alignment and
+ * payload rules as stable_merge.  ws (device, 16-byte aligned) receives the
+ * p_a + p_b subproblem descriptors (and the state of the second-level split)
+ * and must hold stable_merge_pieces_workspace_bytes() bytes
+ * (SM_ERR_WORKSPACE otherwise).
  */
 SM_API int stable_merge_pieces(const void *keys, const uint32_t *payloads, int64_t n, int64_t m,
                                int64_t p_a, int64_t p_b, const int64_t *xbar, const int64_t *ybar,
@@ -137,7 +143,36 @@ SM_API int stable_merge_pieces(const void *keys, const uint32_t *payloads, int64
                                void *ws, size_t ws_bytes, void *stream);
 
 /* Device workspace bytes of stable_merge_pieces (0 on bad arguments). */
-SM_API size_t stable_merge_pieces_workspace_bytes(int64_t p_a, int64_t p_b);
+SM_API size_t stable_merge_pieces_workspace_bytes(int64_t n, int64_t m, int64_t p_a, int64_t p_b,
+                                                  int dtype, int has_payload);
+
+/*
+ * Many independent stable merges in one launch sequence (Section 3: the
+ * merge running on many pairs at once).  Pair k occupies
+ * keys[offsets[k], offsets[k + 1]); its first n_a[k] elements are its A and
+ * the rest its B, and its merge is written to out_keys[offsets[k],
+ * offsets[k + 1]) (payloads alike).  offsets holds count + 1 and n_a count
+ * device int64 entries, with 0 <= offsets[k] <= offsets[k + 1] <= total,
+ * 0 <= n_a[k] <= offsets[k + 1] - offsets[k] and pairs of fewer than 2^30
+ * elements.  A pair that breaks these rules is skipped (its output range is
+ * left unwritten); with options.validate set the call checks the rules and
+ * the sortedness of every A and B first and returns SM_ERR_ARG or
+ * SM_ERR_UNSORTED.  Pairs of any sizes may be mixed: a pair that one
+ * workgroup stages is merged whole, a larger pair is split by the method
+ * with blocks of options.tile elements.  The host never reads offsets or
+ * n_a (except to validate), so the call can be captured in a graph.  keys,
+ * out_keys and payloads follow the rules of stable_merge; ws must hold
+ * stable_merge_batched_workspace_bytes() bytes.
+ */
+SM_API int stable_merge_batched(const void *keys, const uint32_t *payloads,
+                                const int64_t *offsets, const int64_t *n_a, int64_t count,
+                                int64_t total, void *out_keys, uint32_t *out_payloads, int dtype,
+                                void *ws, size_t ws_bytes, const sm_options *opt, void *stream);
+
+/* Device workspace bytes of stable_merge_batched (0 on bad arguments);
+ * options.tile is used, p_a and p_b are ignored. */
+SM_API size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
+                                                   int has_payload, const sm_options *opt);
 
 #ifdef __cplusplus
 }

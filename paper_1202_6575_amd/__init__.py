@@ -20,7 +20,8 @@ import os
 
 import torch
 
-__all__ = ["merge", "partition", "merge_pieces", "workspace_bytes", "SMError", "LIB_PATH", "DTYPES"]
+__all__ = ["merge", "partition", "merge_pieces", "merge_batched", "workspace_bytes",
+           "pieces_workspace_bytes", "batched_workspace_bytes", "SMError", "LIB_PATH", "DTYPES"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstablemerge.so")
 
@@ -62,7 +63,13 @@ _lib.stable_merge_pieces.restype = _i32
 _lib.stable_merge_pieces.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32,
                                      _vp, _sz, _vp]
 _lib.stable_merge_pieces_workspace_bytes.restype = _sz
-_lib.stable_merge_pieces_workspace_bytes.argtypes = [_i64, _i64]
+_lib.stable_merge_pieces_workspace_bytes.argtypes = [_i64, _i64, _i64, _i64, _i32, _i32]
+_lib.stable_merge_batched.restype = _i32
+_lib.stable_merge_batched.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _i32, _vp, _sz,
+                                      ctypes.POINTER(Options), _vp]
+_lib.stable_merge_batched_workspace_bytes.restype = _sz
+_lib.stable_merge_batched_workspace_bytes.argtypes = [_i64, _i64, _i32, _i32,
+                                                      ctypes.POINTER(Options)]
 _lib.stable_merge_partition.restype = _i32
 _lib.stable_merge_partition.argtypes = [_vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp]
 
@@ -98,6 +105,21 @@ def workspace_bytes(n: int, m: int, dtype: torch.dtype, has_payload: bool = Fals
     o = _opts(p_a, p_b, tile)
     return int(_lib.stable_merge_workspace_bytes(n, m, DTYPES[dtype], int(has_payload),
                                                  ctypes.byref(o)))
+
+
+def pieces_workspace_bytes(n: int, m: int, p_a: int, p_b: int, dtype: torch.dtype,
+                           has_payload: bool = False) -> int:
+    """Device workspace bytes stable_merge_pieces needs (0 on bad arguments)."""
+    return int(_lib.stable_merge_pieces_workspace_bytes(n, m, p_a, p_b, DTYPES[dtype],
+                                                        int(has_payload)))
+
+
+def batched_workspace_bytes(count: int, total: int, dtype: torch.dtype,
+                            has_payload: bool = False, tile: int = 0) -> int:
+    """Device workspace bytes stable_merge_batched needs (0 on bad arguments)."""
+    o = _opts(0, 0, tile)
+    return int(_lib.stable_merge_batched_workspace_bytes(count, total, DTYPES[dtype],
+                                                         int(has_payload), ctypes.byref(o)))
 
 
 def _require_device(*ts):
@@ -158,10 +180,11 @@ def merge_pieces(keys: torch.Tensor, n: int, m: int, p_a: int, p_b: int, xbar: t
                  workspace: torch.Tensor | None = None, stream=None):
     """Steps 3-4 given the cross ranks of ``partition`` for the same p_a, p_b."""
     _require_device(keys, payloads, out_keys, out_payloads, xbar, ybar, workspace)
-    if workspace is None:
-        need = int(_lib.stable_merge_pieces_workspace_bytes(p_a, p_b))
-        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
     code = _dtype_code(keys)
+    if workspace is None:
+        need = int(_lib.stable_merge_pieces_workspace_bytes(n, m, p_a, p_b, code,
+                                                            int(payloads is not None)))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
     if out_keys is None:
         out_keys = torch.empty(n + m, dtype=keys.dtype, device=keys.device)
     if payloads is not None and out_payloads is None:
@@ -169,4 +192,38 @@ def merge_pieces(keys: torch.Tensor, n: int, m: int, p_a: int, p_b: int, xbar: t
     _check(_lib.stable_merge_pieces(_ptr(keys), _ptr(payloads), n, m, p_a, p_b, _ptr(xbar),
                                     _ptr(ybar), _ptr(out_keys), _ptr(out_payloads), code,
                                     _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+    return out_keys, out_payloads
+
+
+def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
+                  payloads: torch.Tensor | None = None, *, out_keys: torch.Tensor | None = None,
+                  out_payloads: torch.Tensor | None = None, tile: int = 0,
+                  validate: bool = False, workspace: torch.Tensor | None = None, stream=None):
+    """Independent stable merges of many pairs in one launch sequence.
+
+    Pair k is keys[offsets[k]:offsets[k+1]] with its first n_a[k] elements as
+    A; its merge lands in the same range of out_keys.  offsets (count + 1) and
+    n_a (count) are device int64 tensors.  Returns (out_keys, out_payloads)."""
+    _require_device(keys, offsets, n_a, payloads, out_keys, out_payloads, workspace)
+    if offsets.dtype != torch.int64 or n_a.dtype != torch.int64:
+        raise SMError(-1, "offsets and n_a must be int64")
+    count = n_a.numel()
+    if offsets.numel() != count + 1:
+        raise SMError(-1, "offsets must hold count + 1 entries")
+    total = keys.numel()
+    code = _dtype_code(keys)
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(total, dtype=torch.uint32, device=keys.device)
+    o = _opts(0, 0, tile, validate)
+    if workspace is None:
+        need = int(_lib.stable_merge_batched_workspace_bytes(count, total, code,
+                                                             int(payloads is not None),
+                                                             ctypes.byref(o)))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
+    _check(_lib.stable_merge_batched(_ptr(keys), _ptr(payloads), _ptr(offsets), _ptr(n_a), count,
+                                     total, _ptr(out_keys), _ptr(out_payloads), code,
+                                     _ptr(workspace), workspace.numel(), ctypes.byref(o),
+                                     _stream_ptr(stream)))
     return out_keys, out_payloads

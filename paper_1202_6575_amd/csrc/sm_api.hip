@@ -1,8 +1,12 @@
 // sm_api.hip -- the C ABI of libstablemerge.so (declared in include/stablemerge.h).
 //
-// Host-side argument checks, workspace layout and the launch sequence of the
-// plain stable merge: Steps 1-2 (partition kernel), the single
-// synchronisation (the kernel boundary), Steps 3-4 (merge kernel).
+// Host-side argument checks, workspace layouts and launch sequences.
+// Plain merge: Steps 1-2 (partition kernel), the single synchronisation
+// (the kernel boundary), Steps 3-4 (case selection, then the merges).  When
+// forced block counts make subproblems larger than one workgroup stages,
+// each subproblem becomes a job of the batch engine, which splits it again
+// by the same method (a stable merge of a subproblem is the subproblem's
+// part of the stable merge, Observation 1).
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -11,6 +15,7 @@
 #include <string.h>
 
 #include "stablemerge.h"
+#include "sm_batch.h"
 #include "sm_device.h"
 #include "sm_launch.h"
 
@@ -42,62 +47,93 @@ bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
     return a0 < b0 + bbytes && b0 < a0 + abytes;
 }
 
-// Default top-level block length in elements (the subproblem capacity is
-// about twice this).
-int32_t default_tile(int dtype, bool pay) {
-    if (dtype == SM_UINT64) return pay ? 1024 : 2048;
-    return pay ? 2048 : 2048;
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Block length in elements when none is given: a subproblem then holds up to
+// twice this, and one merge workgroup stages it in LDS.
+int32_t default_tile(int dtype, bool pay) { return dtype == SM_UINT64 && pay ? 1024 : 2048; }
+
+int32_t pick_tile(int dtype, bool pay, const sm_options* opt) {
+    return opt && opt->tile != 0 ? opt->tile : default_tile(dtype, pay);
 }
 
-// Workspace layout of stable_merge: xbar[p_a+1], ybar[p_b+1] (int64), a
-// status word, then p_a + p_b subproblem descriptors.
-size_t ranks_bytes(int64_t pa, int64_t pb) {
-    return ((size_t)(pa + 1 + pb + 1) * sizeof(int64_t) + 255) & ~(size_t)255;
+int check_tile(int dtype, bool pay, int32_t tile) {
+    if (tile < 1 || tile > (1 << 16)) return fail(SM_ERR_ARG, "tile must be in [1, 65536]");
+    if (sm::merge_lds_bytes(dtype, pay, sm::merge_cap_for_tile(tile)) > sm::kMaxLds)
+        return fail(SM_ERR_ARG, "tile %d is too large for one workgroup's LDS", tile);
+    return SM_OK;
 }
+
+// Workspace of stable_merge: xbar[p_a+1] and ybar[p_b+1] (int64), a status
+// word, p_a + p_b subproblem descriptors, and when the subproblems are
+// merged as jobs, the batch engine's workspace.  stable_merge_pieces uses the
+// part from the descriptors on.
+size_t ranks_bytes(int64_t pa, int64_t pb) { return align256((size_t)(pa + 1 + pb + 1) * 8); }
 
 struct Plan {
     int64_t p_a, p_b;
-    uint32_t cap;
-    uint32_t lds;
-    size_t ws_bytes;
+    int32_t tile;
+    uint32_t cap;  // capacity (elements) of one merge workgroup's subproblem
+    bool hier;     // subproblems exceed cap: merge them as jobs of the engine
+    sm::BatchLayout layout;
+    size_t off_flag, off_desc, off_batch, ws_bytes;
 };
 
-// Chooses block counts and checks that one workgroup can hold a subproblem.
-int make_plan(int64_t n, int64_t m, int dtype, bool pay, const sm_options* opt, Plan* pl) {
-    if (n < 0 || m < 0) return fail(SM_ERR_ARG, "n and m must be >= 0 (n=%lld, m=%lld)",
-                                    (long long)n, (long long)m);
+int check_sizes(int64_t n, int64_t m, int dtype) {
+    if (n < 0 || m < 0)
+        return fail(SM_ERR_ARG, "n and m must be >= 0 (n=%lld, m=%lld)", (long long)n, (long long)m);
     if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
     if ((uint64_t)(n + m) > (1ull << 40)) return fail(SM_ERR_ARG, "n + m too large");
-    int64_t pa = opt ? opt->p_a : 0, pb = opt ? opt->p_b : 0;
-    int32_t tile = opt && opt->tile > 0 ? opt->tile : default_tile(dtype, pay);
+    return SM_OK;
+}
+
+// Block counts, subproblem capacity and workspace layout of one merge.
+int make_plan(int64_t n, int64_t m, int dtype, bool pay, int64_t pa, int64_t pb, int32_t tile,
+              Plan* pl) {
+    int rc = check_sizes(n, m, dtype);
+    if (rc != SM_OK) return rc;
     if (pa < 0 || pb < 0) return fail(SM_ERR_ARG, "p_a and p_b must be >= 0");
-    if (tile < 1) return fail(SM_ERR_ARG, "tile must be >= 1");
+    rc = check_tile(dtype, pay, tile);
+    if (rc != SM_OK) return rc;
     if (pa == 0) pa = n > 0 ? (n + tile - 1) / tile : 1;
     if (pb == 0) pb = m > 0 ? (m + tile - 1) / tile : 1;
     if (pa > (1ll << 31) - 2 || pb > (1ll << 31) - 2 || pa + pb > (1ll << 31) - 2)
         return fail(SM_ERR_ARG, "too many blocks (p_a=%lld, p_b=%lld)", (long long)pa,
                     (long long)pb);
-    // every subproblem holds at most ceil(n/p_a) + ceil(m/p_b) elements
-    const int64_t cap = (n + pa - 1) / pa + (m + pb - 1) / pb;
-    const uint32_t lds = sm::merge_lds_bytes(dtype, pay, (uint32_t)(cap < (1 << 20) ? cap : (1 << 20)));
-    if (cap >= (1 << 20) || lds > sm::kMaxLds)
-        return fail(SM_ERR_ARG,
-                    "subproblems of up to %lld elements do not fit one workgroup's LDS "
-                    "(%u bytes > %u); use more blocks",
-                    (long long)cap, lds, sm::kMaxLds);
+    // a subproblem holds at most one block of A and one block of B
+    const int64_t la = (n + pa - 1) / pa, lb = (m + pb - 1) / pb;
+    if (la >= (1ll << 31) || lb >= (1ll << 31))
+        return fail(SM_ERR_ARG, "blocks of more than 2^31 - 1 elements; use more blocks");
+    // subproblems that one workgroup stages are merged directly, larger ones
+    // are split again with blocks of `tile` elements
+    const int64_t sub = la + lb > 0 ? la + lb : 1;
     pl->p_a = pa;
     pl->p_b = pb;
-    pl->cap = (uint32_t)(cap > 0 ? cap : 1);
-    pl->lds = lds;
-    pl->ws_bytes = ranks_bytes(pa, pb) + 256 + (size_t)(pa + pb) * sm::kPieceDescBytes;
+    pl->tile = tile;
+    pl->hier = sub >= (1 << 20) || sm::merge_lds_bytes(dtype, pay, (uint32_t)sub) > sm::kMaxLds;
+    pl->cap = pl->hier ? sm::merge_cap_for_tile(tile) : (uint32_t)sub;
+    size_t off = ranks_bytes(pa, pb);
+    pl->off_flag = off;
+    off += 256;
+    pl->off_desc = off;
+    off += align256((size_t)(pa + pb) * sm::kPieceDescBytes);
+    pl->off_batch = off;
+    if (pl->hier) {
+        pl->layout = sm::batch_layout(pa + pb, n + m, tile);
+        if (pl->layout.p_max > (1ll << 31) - 2)
+            return fail(SM_ERR_ARG, "too many second-level subproblems; use a larger tile");
+        off += pl->layout.bytes;
+    }
+    pl->ws_bytes = off;
     return SM_OK;
 }
 
-
-// Checks shared by stable_merge and stable_merge_pieces.
+// Checks shared by the entry points that write a merged array.
 int check_buffers(const void* keys, const uint32_t* payloads, int64_t total, void* out_keys,
                   uint32_t* out_payloads, int dtype) {
     const bool pay = payloads != nullptr;
+    if ((payloads == nullptr) != (out_payloads == nullptr))
+        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
     if (!keys || !out_keys) return fail(SM_ERR_ARG, "keys and out_keys must not be NULL");
     if (!aligned16(keys) || !aligned16(out_keys) ||
         (pay && (!aligned16(payloads) || !aligned16(out_payloads))))
@@ -111,25 +147,56 @@ int check_buffers(const void* keys, const uint32_t* payloads, int64_t total, voi
     return SM_OK;
 }
 
+int check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (!ws || ws_bytes < need)
+        return fail(SM_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                    ws ? ws_bytes : (size_t)0);
+    if (!aligned16(ws)) return fail(SM_ERR_ARG, "workspace must be 16-byte aligned");
+    return SM_OK;
+}
+
+// Steps 3-4 and the merges, once Steps 1-2 have written xbar / ybar.
+// `tail` is the workspace from the descriptors on.
+int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t* payloads,
+                    int64_t n, int64_t m, const int64_t* xbar, const int64_t* ybar,
+                    void* out_keys, uint32_t* out_payloads, char* tail, hipStream_t st) {
+    sm::PieceDesc* desc = reinterpret_cast<sm::PieceDesc*>(tail);
+    const int64_t P = pl.p_a + pl.p_b;
+    hipError_t e = sm::launch_cases(n, m, pl.p_a, pl.p_b, xbar, ybar, desc, st);
+    if (e != hipSuccess) return hip_fail(e, "cases launch");
+    if (!pl.hier)
+        e = sm::launch_merge_desc(dtype, keys, payloads, n + m, out_keys, out_payloads, n + m, desc,
+                                  P, nullptr, pl.cap, st);
+    else
+        e = sm::launch_batch(dtype, keys, payloads, n + m, out_keys, out_payloads, n + m, desc, P,
+                             pl.tile, tail + (pl.off_batch - pl.off_desc), pl.layout, st);
+    if (e != hipSuccess) return hip_fail(e, "merge launch");
+    return SM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* sm_last_error(void) { return g_err; }
 
-int sm_version(void) { return 100; }
+int sm_version(void) { return 200; }
 
 size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
                                     const sm_options* opt) {
     Plan pl;
-    if (make_plan(n, m, dtype, has_payload != 0, opt, &pl) != SM_OK) return 0;
+    if (!dtype_ok(dtype)) return 0;
+    const bool pay = has_payload != 0;
+    if (make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
+                  pick_tile(dtype, pay, opt), &pl) != SM_OK)
+        return 0;
     return pl.ws_bytes;
 }
 
 int stable_merge_partition(const void* keys, int64_t n, int64_t m, int64_t p_a, int64_t p_b,
                            int dtype, int64_t* xbar, int64_t* ybar, void* stream) {
-    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
-    if (n < 0 || m < 0) return fail(SM_ERR_ARG, "n and m must be >= 0");
+    int rc = check_sizes(n, m, dtype);
+    if (rc != SM_OK) return rc;
     if (p_a < 1 || p_b < 1) return fail(SM_ERR_ARG, "p_a and p_b must be >= 1");
     if (p_a + p_b > (1ll << 40)) return fail(SM_ERR_ARG, "too many blocks");
     if (!xbar || !ybar) return fail(SM_ERR_ARG, "xbar and ybar must not be NULL");
@@ -142,73 +209,60 @@ int stable_merge_partition(const void* keys, int64_t n, int64_t m, int64_t p_a, 
     return SM_OK;
 }
 
-
-size_t stable_merge_pieces_workspace_bytes(int64_t p_a, int64_t p_b) {
-    if (p_a < 1 || p_b < 1 || p_a + p_b > (1ll << 40)) return 0;
-    return (size_t)(p_a + p_b) * sm::kPieceDescBytes;
+size_t stable_merge_pieces_workspace_bytes(int64_t n, int64_t m, int64_t p_a, int64_t p_b,
+                                           int dtype, int has_payload) {
+    Plan pl;
+    if (!dtype_ok(dtype) || p_a < 1 || p_b < 1) return 0;
+    const bool pay = has_payload != 0;
+    if (make_plan(n, m, dtype, pay, p_a, p_b, default_tile(dtype, pay), &pl) != SM_OK) return 0;
+    return pl.ws_bytes - pl.off_desc;
 }
 
 int stable_merge_pieces(const void* keys, const uint32_t* payloads, int64_t n, int64_t m,
                         int64_t p_a, int64_t p_b, const int64_t* xbar, const int64_t* ybar,
                         void* out_keys, uint32_t* out_payloads, int dtype, void* ws,
                         size_t ws_bytes, void* stream) {
-    if ((payloads == nullptr) != (out_payloads == nullptr))
-        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
     if (p_a < 1 || p_b < 1) return fail(SM_ERR_ARG, "p_a and p_b must be >= 1");
-    sm_options o;
-    memset(&o, 0, sizeof o);
-    o.p_a = p_a;
-    o.p_b = p_b;
+    const bool pay = payloads != nullptr;
     Plan pl;
-    int rc = make_plan(n, m, dtype, payloads != nullptr, &o, &pl);
+    int rc = make_plan(n, m, dtype, pay, p_a, p_b, default_tile(dtype, pay), &pl);
     if (rc != SM_OK) return rc;
     if (n + m == 0) return SM_OK;
     if (!xbar || !ybar) return fail(SM_ERR_ARG, "xbar and ybar must not be NULL");
     rc = check_buffers(keys, payloads, n + m, out_keys, out_payloads, dtype);
     if (rc != SM_OK) return rc;
-    const size_t need = (size_t)(pl.p_a + pl.p_b) * sm::kPieceDescBytes;
-    if (!ws || ws_bytes < need)
-        return fail(SM_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
-                    ws ? ws_bytes : (size_t)0);
-    if (!aligned16(ws)) return fail(SM_ERR_ARG, "workspace must be 16-byte aligned");
-    hipError_t e = sm::launch_merge(dtype, keys, payloads, n, m, pl.p_a, pl.p_b, xbar, ybar,
-                                    static_cast<sm::PieceDesc*>(ws), out_keys, out_payloads,
-                                    pl.cap, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "merge launch");
-    return SM_OK;
+    rc = check_ws(ws, ws_bytes, pl.ws_bytes - pl.off_desc);
+    if (rc != SM_OK) return rc;
+    return cases_and_merge(pl, dtype, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
+                           static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
 int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t m, void* out_keys,
                  uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
                  const sm_options* opt, void* stream) {
     const bool pay = payloads != nullptr;
-    if ((payloads == nullptr) != (out_payloads == nullptr))
-        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
     Plan pl;
-    int rc = make_plan(n, m, dtype, pay, opt, &pl);
+    int rc = make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
+                       pick_tile(dtype, pay, opt), &pl);
     if (rc != SM_OK) return rc;
     const int64_t total = n + m;
     if (total == 0) return SM_OK;
     rc = check_buffers(keys, payloads, total, out_keys, out_payloads, dtype);
     if (rc != SM_OK) return rc;
-    if (!ws || ws_bytes < pl.ws_bytes)
-        return fail(SM_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.ws_bytes,
-                    ws ? ws_bytes : (size_t)0);
-    if (!aligned16(ws)) return fail(SM_ERR_ARG, "workspace must be 16-byte aligned");
+    rc = check_ws(ws, ws_bytes, pl.ws_bytes);
+    if (rc != SM_OK) return rc;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int64_t* xbar = static_cast<int64_t*>(ws);
+    char* w = static_cast<char*>(ws);
+    int64_t* xbar = reinterpret_cast<int64_t*>(w);
     int64_t* ybar = xbar + (pl.p_a + 1);
-    int* flag = reinterpret_cast<int*>(static_cast<char*>(ws) + ranks_bytes(pl.p_a, pl.p_b));
-    sm::PieceDesc* desc = reinterpret_cast<sm::PieceDesc*>(static_cast<char*>(ws) +
-                                                           ranks_bytes(pl.p_a, pl.p_b) + 256);
+    int* flag = reinterpret_cast<int*>(w + pl.off_flag);
     hipError_t e;
 
     if (opt && opt->validate) {
         int host_flag = 0;
-        e = hipMemsetAsync(flag, 0, sizeof(int), st);
-        if (e != hipSuccess) return hip_fail(e, "validate memset");
-        e = sm::launch_validate(dtype, keys, n, m, flag, st);
+        e = sm::launch_clear(flag, 1, st);
+        if (e == hipSuccess) e = sm::launch_validate(dtype, keys, n, m, flag, st);
         if (e != hipSuccess) return hip_fail(e, "validate launch");
         e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -218,9 +272,66 @@ int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t 
 
     e = sm::launch_partition(dtype, keys, n, m, pl.p_a, pl.p_b, xbar, ybar, st);
     if (e != hipSuccess) return hip_fail(e, "partition launch");
-    e = sm::launch_merge(dtype, keys, payloads, n, m, pl.p_a, pl.p_b, xbar, ybar, desc, out_keys,
-                         out_payloads, pl.cap, st);
-    if (e != hipSuccess) return hip_fail(e, "merge launch");
+    return cases_and_merge(pl, dtype, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
+                           w + pl.off_desc, st);
+}
+
+size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
+                                            int has_payload, const sm_options* opt) {
+    if (!dtype_ok(dtype) || count < 0 || total < 0 || total > (1ll << 40)) return 0;
+    const bool pay = has_payload != 0;
+    const int32_t tile = pick_tile(dtype, pay, opt);
+    if (check_tile(dtype, pay, tile) != SM_OK) return 0;
+    const sm::BatchLayout L = sm::batch_layout(count, total, tile);
+    return align256((size_t)count * sm::kPieceDescBytes) + L.bytes;
+}
+
+int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64_t* offsets,
+                         const int64_t* n_a, int64_t count, int64_t total, void* out_keys,
+                         uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                         const sm_options* opt, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (count < 0 || total < 0 || total > (1ll << 40))
+        return fail(SM_ERR_ARG, "count and total must be >= 0 (count=%lld, total=%lld)",
+                    (long long)count, (long long)total);
+    if (count > (1ll << 31) - 2) return fail(SM_ERR_ARG, "too many pairs");
+    const bool pay = payloads != nullptr;
+    const int32_t tile = pick_tile(dtype, pay, opt);
+    int rc = check_tile(dtype, pay, tile);
+    if (rc != SM_OK) return rc;
+    if (count == 0 || total == 0) return SM_OK;
+    if (!offsets || !n_a) return fail(SM_ERR_ARG, "offsets and n_a must not be NULL");
+    rc = check_buffers(keys, payloads, total, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    const sm::BatchLayout L = sm::batch_layout(count, total, tile);
+    if (L.p_max > (1ll << 31) - 2)
+        return fail(SM_ERR_ARG, "too many subproblems for one launch; use a larger tile");
+    const size_t off_eng = align256((size_t)count * sm::kPieceDescBytes);
+    rc = check_ws(ws, ws_bytes, off_eng + L.bytes);
+    if (rc != SM_OK) return rc;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    sm::PieceDesc* jobs = reinterpret_cast<sm::PieceDesc*>(w);
+    int* flag = reinterpret_cast<int*>(w + off_eng + L.off_flag);
+    hipError_t e = sm::launch_clear(flag, 1, st);
+    if (e == hipSuccess) e = sm::launch_jobs_from_pairs(offsets, n_a, count, total, jobs, flag, st);
+    if (e != hipSuccess) return hip_fail(e, "pair descriptor launch");
+    if (opt && opt->validate) {
+        int host_flag = 0;
+        e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "validate readback");
+        if (host_flag) return fail(SM_ERR_ARG, "offsets / n_a describe an invalid pair");
+        e = sm::launch_batch_validate(dtype, keys, offsets, n_a, count, total, flag, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "validate readback");
+        if (host_flag) return fail(SM_ERR_UNSORTED, "an A or B of the batch is not non-decreasing");
+    }
+    e = sm::launch_batch(dtype, keys, payloads, total, out_keys, out_payloads, total, jobs, count,
+                         tile, w + off_eng, L, st);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
     return SM_OK;
 }
 

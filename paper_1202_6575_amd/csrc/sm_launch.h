@@ -33,10 +33,19 @@ hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const in
                         const int64_t* ybar, PieceDesc* desc, hipStream_t st);
 
 // Merges of P subproblem descriptors (keys / payload positions index arrays
-// of nkeys elements; outputs index arrays of nout elements).
+// of nkeys elements; outputs index arrays of nout elements).  If P_dev is
+// not null the count is read from device memory and P is its upper bound.
 hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
                              void* out_keys, uint32_t* out_pay, int64_t nout,
-                             const PieceDesc* desc, int64_t P, uint32_t cap, hipStream_t st);
+                             const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
+                             hipStream_t st);
+
+// Subproblem capacity (elements) that one merge workgroup can stage for a
+// key type, in the register-pipelined kernel at the default tile.
+uint32_t merge_cap_for_tile(int32_t tile);
+
+// Number of compute units of the current device.
+int device_cu_count();
 
 constexpr size_t kPieceDescBytes = 32;
 

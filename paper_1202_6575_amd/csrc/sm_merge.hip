@@ -72,9 +72,15 @@ template <typename K, bool PAY, int L, int R>
 __global__ __launch_bounds__(L) void merge_persistent_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
-    const PieceDesc* __restrict__ desc, int64_t P, uint32_t cap) {
+    const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
     extern __shared__ __align__(16) char smem[];
     const SmemPtrs<K, PAY, L> sp(smem, cap);
+    // the subproblem count comes from device memory when it was computed there
+    // (batched merges); P is then its upper bound
+    if (P_dev) {
+        const int64_t pd = *P_dev;
+        P = pd < P ? (pd > 0 ? pd : 0) : P;
+    }
     const int64_t G = gridDim.x;
     const int64_t w0 = (int64_t)blockIdx.x * P / G;
     const int64_t w1 = ((int64_t)blockIdx.x + 1) * P / G;
@@ -117,9 +123,10 @@ template <typename K, bool PAY, int L>
 __global__ __launch_bounds__(L) void merge_direct_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
-    const PieceDesc* __restrict__ desc, int64_t P, uint32_t cap) {
+    const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
     extern __shared__ __align__(16) char smem[];
     const SmemPtrs<K, PAY, L> sp(smem, cap);
+    if (P_dev && (int64_t)blockIdx.x >= *P_dev) return;
     const PieceDesc d = desc[blockIdx.x];
     if (!desc_ok(d, nkeys, nout, cap) || desc_a(d) + desc_b(d) == 0) return;
     const SegPlan p = make_plan<K, PAY>(d);
@@ -171,7 +178,7 @@ hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m, i
     return hipGetLastError();
 }
 
-static int cu_count() {
+int device_cu_count() {
     static int cus = 0;
     if (cus == 0) {
         int dev = 0;
@@ -204,7 +211,7 @@ static bool fits_regs(uint32_t cap, int R) {
 template <typename K, bool PAY, int R>
 static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t nkeys, K* out,
                                     uint32_t* out_pay, int64_t nout, const PieceDesc* desc,
-                                    int64_t P, uint32_t cap, hipStream_t st) {
+                                    int64_t P, const int64_t* P_dev, uint32_t cap, hipStream_t st) {
     constexpr int L = kMergeThreads;
     auto kern = merge_persistent_kernel<K, PAY, L, R>;
     static bool attr = false;
@@ -217,23 +224,26 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
     int per_cu = (int)(kMaxLds / lds);
     if (per_cu > 8) per_cu = 8;
     if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)cu_count() * per_cu;
+    int64_t grid = (int64_t)device_cu_count() * per_cu;
     if (grid > P) grid = P;
-    kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap);
+    kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
     return hipGetLastError();
 }
 
 template <typename K, bool PAY>
 static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_t nkeys,
                                  void* out_v, uint32_t* out_pay, int64_t nout,
-                                 const PieceDesc* desc, int64_t P, uint32_t cap, hipStream_t st) {
+                                 const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
+                                 hipStream_t st) {
     const K* keys = static_cast<const K*>(keys_v);
     K* out = static_cast<K*>(out_v);
     if (P <= 0) return hipSuccess;
     if (fits_regs<K, PAY>(cap, 5))
-        return launch_persistent<K, PAY, 5>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap, st);
+        return launch_persistent<K, PAY, 5>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap,
+                                            st);
     if (fits_regs<K, PAY>(cap, 9))
-        return launch_persistent<K, PAY, 9>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap, st);
+        return launch_persistent<K, PAY, 9>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap,
+                                            st);
     constexpr int L = kMergeThreads;
     auto kern = merge_direct_kernel<K, PAY, L>;
     static bool attr = false;
@@ -243,9 +253,11 @@ static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_
         attr = true;
     }
     const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
-    kern<<<(unsigned)P, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, cap);
+    kern<<<(unsigned)P, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
     return hipGetLastError();
 }
+
+uint32_t merge_cap_for_tile(int32_t tile) { return 2u * (uint32_t)tile; }
 
 hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                         const int64_t* ybar, PieceDesc* desc, hipStream_t st) {
@@ -256,13 +268,15 @@ hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const in
 
 hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
                              void* out_keys, uint32_t* out_pay, int64_t nout,
-                             const PieceDesc* desc, int64_t P, uint32_t cap, hipStream_t st) {
+                             const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
+                             hipStream_t st) {
     hipError_t e = hipSuccess;
     with_dtype(dtype, [&](auto z) {
         using K = decltype(z);
-        e = pay ? launch_merge_t<K, true>(keys, pay, nkeys, out_keys, out_pay, nout, desc, P, cap, st)
+        e = pay ? launch_merge_t<K, true>(keys, pay, nkeys, out_keys, out_pay, nout, desc, P, P_dev,
+                                          cap, st)
                 : launch_merge_t<K, false>(keys, nullptr, nkeys, out_keys, nullptr, nout, desc, P,
-                                           cap, st);
+                                           P_dev, cap, st);
     });
     return e;
 }
@@ -274,7 +288,7 @@ hipError_t launch_merge(int dtype, const void* keys, const uint32_t* pay, int64_
     hipError_t e = launch_cases(n, m, p_a, p_b, xbar, ybar, desc, st);
     if (e != hipSuccess) return e;
     return launch_merge_desc(dtype, keys, pay, n + m, out_keys, out_pay, n + m, desc, p_a + p_b,
-                             cap, st);
+                             nullptr, cap, st);
 }
 
 hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, int* flag,

@@ -60,8 +60,11 @@ def test_error_paths(sm):
     o.p_a = -3
     assert call_merge(sm, opts=o) == -1
     o = sm.Options()
-    o.p_a, o.p_b = 1, 1                                            # subproblem too big for LDS
-    assert call_merge(sm, n=1 << 22, m=1 << 22, opts=o) == -1
+    o.tile = 1 << 15                                               # subproblem too big for LDS
+    assert call_merge(sm, opts=o) == -1
+    o = sm.Options()
+    o.tile = -5
+    assert call_merge(sm, opts=o) == -1
     assert call_merge(sm, n=0, m=0) == 0                           # nothing to do
 
 
@@ -77,7 +80,33 @@ def test_workspace_bytes(sm):
     w = sm.workspace_bytes(1 << 20, 1 << 19, torch.uint32)
     assert w >= ((1 << 20) // 2048 + (1 << 19) // 2048 + 2) * 8
     assert sm.workspace_bytes(-1, 3, torch.uint32) == 0
-    assert sm.workspace_bytes(100, 100, torch.uint32, p_a=5, p_b=5) == 256 + 256 + 10 * 32
+    assert sm.workspace_bytes(100, 100, torch.uint32, p_a=5, p_b=5) == 256 + 256 + 512
+    # forced p with subproblems beyond one workgroup: the second-level state is added
+    big = sm.workspace_bytes(1 << 20, 1 << 20, torch.uint32, p_a=2, p_b=2)
+    assert big > 256 + 256 + 256 + ((1 << 21) // 2048) * 32
+    assert sm.pieces_workspace_bytes(100, 100, 5, 5, torch.uint32) == 512
+    assert sm.pieces_workspace_bytes(100, 100, 0, 5, torch.uint32) == 0
+    assert sm.batched_workspace_bytes(10, 1000, torch.uint32) > 10 * 32
+    assert sm.batched_workspace_bytes(-1, 1000, torch.uint32) == 0
+
+
+def test_batched_error_paths(sm):
+    f = sm._lib.stable_merge_batched
+    o = sm.Options()
+    args = dict(keys=0x10000, pay=None, offs=0x50000, na=0x60000, count=4, total=100,
+                out=0x20000, opay=None, dtype=1, ws=0x30000, ws_bytes=1 << 20)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return f(a["keys"], a["pay"], a["offs"], a["na"], a["count"], a["total"], a["out"],
+                 a["opay"], a["dtype"], a["ws"], a["ws_bytes"], ctypes.byref(o), None)
+    assert call(dtype=5) == -2
+    assert call(count=-1) == -1
+    assert call(offs=None) == -1
+    assert call(out=0x10000) == -3
+    assert call(ws_bytes=16) == -4
+    assert call(count=0) == 0
+    assert call(total=0) == 0
 
 
 def test_version(sm):

@@ -110,13 +110,25 @@ def test_several_tiles_ragged(dtype, with_pay):
         check(A, B, with_pay)
 
 
-@pytest.mark.parametrize("p", [2, 5, 17, 256])
+@pytest.mark.parametrize("p", [1, 2, 5, 17, 256])
 def test_forced_p(p):
     g = np.random.default_rng(p)
     A, B = rand_sorted(g, 20_000, 100, np.uint32), rand_sorted(g, 9_000, 100, np.uint32)
     flush(f"forced p={p}")
     check(A, B, True, p_a=p, p_b=p)
     check(A, B, False, p_a=p, p_b=max(1, p // 2))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_forced_few_blocks_large(dtype):
+    """Few forced blocks over large arrays: subproblems far beyond one
+    workgroup are split again by the method (two levels)."""
+    g = np.random.default_rng(41)
+    A, B = rand_sorted(g, 300_001, 1000, dtype), rand_sorted(g, 200_003, 1000, dtype)
+    for pa, pb in [(1, 1), (2, 3), (7, 1)]:
+        flush(f"forced large dtype={np.dtype(dtype).name} p_a={pa} p_b={pb}")
+        check(A, B, True, p_a=pa, p_b=pb)
+        check(A, B, False, p_a=pa, p_b=pb, tile=100)
 
 
 def test_tiling_independence():
