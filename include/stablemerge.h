@@ -71,13 +71,18 @@ typedef enum {
  *             subproblems exceed 2 * tile are split again with this tile.
  *  validate   nonzero: first check that A and B are non-decreasing (one extra
  *             read of the keys and a synchronisation with the host).
+ *  run        stable_merge_sort only: length of the runs sorted inside one
+ *             workgroup before the merge passes; 256, 512, 1024 or 2048
+ *             (0 = 512).
+ *  reserved   must be zero.
  */
 typedef struct {
     int64_t p_a;
     int64_t p_b;
     int32_t tile;
     int32_t validate;
-    int32_t reserved[6];
+    int32_t run;
+    int32_t reserved[5];
 } sm_options;
 
 /* Message describing the last non-OK status returned on this thread. */
@@ -173,6 +178,26 @@ SM_API int stable_merge_batched(const void *keys, const uint32_t *payloads,
  * options.tile is used, p_a and p_b are ignored. */
 SM_API size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
                                                    int has_payload, const sm_options *opt);
+
+/*
+ * Stable merge sort (Section 3: sorting by repeated stable merging).
+ * Sorts keys[0, N) into out_keys[0, N); payloads (optional) travel with
+ * their keys.  Equal keys keep their input order.  Runs of options.run
+ * elements are first sorted inside one workgroup each (by cross ranks with
+ * blocks of one element), then ceil(log2(N / run)) passes each merge pairs
+ * of neighbouring runs with the stable merge.  out_keys may be keys itself
+ * (in-place sort; likewise out_payloads and payloads), any other overlap is
+ * SM_ERR_ALIAS.  0 <= N < 2^31.  ws must hold
+ * stable_merge_sort_workspace_bytes() bytes: a second buffer of N keys (and
+ * N payloads) for the passes to alternate with, plus the merge state.
+ */
+SM_API int stable_merge_sort(const void *keys, const uint32_t *payloads, int64_t N,
+                             void *out_keys, uint32_t *out_payloads, int dtype,
+                             void *ws, size_t ws_bytes, const sm_options *opt, void *stream);
+
+/* Device workspace bytes of stable_merge_sort (0 on bad arguments). */
+SM_API size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_payload,
+                                                const sm_options *opt);
 
 #ifdef __cplusplus
 }

@@ -20,8 +20,8 @@ import os
 
 import torch
 
-__all__ = ["merge", "partition", "merge_pieces", "merge_batched", "workspace_bytes",
-           "pieces_workspace_bytes", "batched_workspace_bytes", "SMError", "LIB_PATH", "DTYPES"]
+__all__ = ["merge", "partition", "merge_pieces", "merge_batched", "sort", "workspace_bytes",
+           "pieces_workspace_bytes", "batched_workspace_bytes", "sort_workspace_bytes", "SMError", "LIB_PATH", "DTYPES"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstablemerge.so")
 
@@ -47,7 +47,8 @@ class SMError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("p_a", ctypes.c_int64), ("p_b", ctypes.c_int64), ("tile", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("validate", ctypes.c_int32), ("run", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
@@ -70,6 +71,11 @@ _lib.stable_merge_batched.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, 
 _lib.stable_merge_batched_workspace_bytes.restype = _sz
 _lib.stable_merge_batched_workspace_bytes.argtypes = [_i64, _i64, _i32, _i32,
                                                       ctypes.POINTER(Options)]
+_lib.stable_merge_sort.restype = _i32
+_lib.stable_merge_sort.argtypes = [_vp, _vp, _i64, _vp, _vp, _i32, _vp, _sz,
+                                   ctypes.POINTER(Options), _vp]
+_lib.stable_merge_sort_workspace_bytes.restype = _sz
+_lib.stable_merge_sort_workspace_bytes.argtypes = [_i64, _i32, _i32, ctypes.POINTER(Options)]
 _lib.stable_merge_partition.restype = _i32
 _lib.stable_merge_partition.argtypes = [_vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp]
 
@@ -95,8 +101,8 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(p_a=0, p_b=0, tile=0, validate=False) -> Options:
-    return Options(int(p_a), int(p_b), int(tile), int(bool(validate)))
+def _opts(p_a=0, p_b=0, tile=0, validate=False, run=0) -> Options:
+    return Options(int(p_a), int(p_b), int(tile), int(bool(validate)), int(run))
 
 
 def workspace_bytes(n: int, m: int, dtype: torch.dtype, has_payload: bool = False,
@@ -120,6 +126,14 @@ def batched_workspace_bytes(count: int, total: int, dtype: torch.dtype,
     o = _opts(0, 0, tile)
     return int(_lib.stable_merge_batched_workspace_bytes(count, total, DTYPES[dtype],
                                                          int(has_payload), ctypes.byref(o)))
+
+
+def sort_workspace_bytes(N: int, dtype: torch.dtype, has_payload: bool = False, run: int = 0,
+                         tile: int = 0) -> int:
+    """Device workspace bytes stable_merge_sort needs (0 on bad arguments)."""
+    o = _opts(0, 0, tile, False, run)
+    return int(_lib.stable_merge_sort_workspace_bytes(N, DTYPES[dtype], int(has_payload),
+                                                      ctypes.byref(o)))
 
 
 def _require_device(*ts):
@@ -226,4 +240,27 @@ def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
                                      total, _ptr(out_keys), _ptr(out_payloads), code,
                                      _ptr(workspace), workspace.numel(), ctypes.byref(o),
                                      _stream_ptr(stream)))
+    return out_keys, out_payloads
+
+
+def sort(keys: torch.Tensor, payloads: torch.Tensor | None = None, *,
+         out_keys: torch.Tensor | None = None, out_payloads: torch.Tensor | None = None,
+         run: int = 0, tile: int = 0, workspace: torch.Tensor | None = None, stream=None):
+    """Stable merge sort of keys (payloads travel along).  Passing the inputs
+    as out_keys / out_payloads sorts in place.  Returns (out_keys, out_payloads)."""
+    _require_device(keys, payloads, out_keys, out_payloads, workspace)
+    N = keys.numel()
+    code = _dtype_code(keys)
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(N, dtype=torch.uint32, device=keys.device)
+    o = _opts(0, 0, tile, False, run)
+    if workspace is None:
+        need = int(_lib.stable_merge_sort_workspace_bytes(N, code, int(payloads is not None),
+                                                          ctypes.byref(o)))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
+    _check(_lib.stable_merge_sort(_ptr(keys), _ptr(payloads), N, _ptr(out_keys),
+                                  _ptr(out_payloads), code, _ptr(workspace), workspace.numel(),
+                                  ctypes.byref(o), _stream_ptr(stream)))
     return out_keys, out_payloads

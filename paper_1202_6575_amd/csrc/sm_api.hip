@@ -18,6 +18,7 @@
 #include "sm_batch.h"
 #include "sm_device.h"
 #include "sm_launch.h"
+#include "sm_sort.h"
 
 namespace {
 
@@ -102,8 +103,8 @@ int make_plan(int64_t n, int64_t m, int dtype, bool pay, int64_t pa, int64_t pb,
                     (long long)pb);
     // a subproblem holds at most one block of A and one block of B
     const int64_t la = (n + pa - 1) / pa, lb = (m + pb - 1) / pb;
-    if (la >= (1ll << 31) || lb >= (1ll << 31))
-        return fail(SM_ERR_ARG, "blocks of more than 2^31 - 1 elements; use more blocks");
+    if (la >= (1ll << 30) || lb >= (1ll << 30))
+        return fail(SM_ERR_ARG, "blocks of 2^30 or more elements; use more blocks");
     // subproblems that one workgroup stages are merged directly, larger ones
     // are split again with blocks of `tile` elements
     const int64_t sub = la + lb > 0 ? la + lb : 1;
@@ -332,6 +333,69 @@ int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64
     e = sm::launch_batch(dtype, keys, payloads, total, out_keys, out_payloads, total, jobs, count,
                          tile, w + off_eng, L, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return SM_OK;
+}
+
+namespace {
+
+int sort_plan(int64_t N, int dtype, bool pay, const sm_options* opt, int* run, int32_t* tile,
+              sm::SortLayout* L) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (N < 0 || N >= (1ll << 31)) return fail(SM_ERR_ARG, "N must be in [0, 2^31)");
+    *run = opt && opt->run != 0 ? opt->run : 512;
+    if (!sm::sort_run_ok(*run)) return fail(SM_ERR_ARG, "run must be 256, 512, 1024 or 2048");
+    *tile = pick_tile(dtype, pay, opt);
+    int rc = check_tile(dtype, pay, *tile);
+    if (rc != SM_OK) return rc;
+    *L = sm::sort_layout(N, dtype, pay, *run, *tile);
+    if (L->batch.p_max > (1ll << 31) - 2)
+        return fail(SM_ERR_ARG, "too many subproblems per pass; use a larger tile");
+    return SM_OK;
+}
+
+}  // namespace
+
+size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_payload,
+                                         const sm_options* opt) {
+    int run;
+    int32_t tile;
+    sm::SortLayout L;
+    if (sort_plan(N, dtype, has_payload != 0, opt, &run, &tile, &L) != SM_OK) return 0;
+    return L.bytes;
+}
+
+int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                      const sm_options* opt, void* stream) {
+    const bool pay = payloads != nullptr;
+    int run;
+    int32_t tile;
+    sm::SortLayout L;
+    int rc = sort_plan(N, dtype, pay, opt, &run, &tile, &L);
+    if (rc != SM_OK) return rc;
+    if ((payloads == nullptr) != (out_payloads == nullptr))
+        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
+    if (N == 0) return SM_OK;
+    if (!keys || !out_keys) return fail(SM_ERR_ARG, "keys and out_keys must not be NULL");
+    if (!aligned16(keys) || !aligned16(out_keys) ||
+        (pay && (!aligned16(payloads) || !aligned16(out_payloads))))
+        return fail(SM_ERR_ARG, "device arrays must be 16-byte aligned");
+    const size_t kb = (size_t)N * key_bytes(dtype), pb = (size_t)N * 4;
+    // the same array in and out is an in-place sort; a partial overlap is not
+    if ((out_keys != keys && overlap(out_keys, kb, keys, kb)) ||
+        (pay && ((out_payloads != payloads && overlap(out_payloads, pb, payloads, pb)) ||
+                 overlap(out_payloads, pb, keys, kb) || overlap(out_keys, kb, payloads, pb) ||
+                 overlap(out_keys, kb, out_payloads, pb))))
+        return fail(SM_ERR_ALIAS, "outputs overlap inputs other than in place");
+    rc = check_ws(ws, ws_bytes, L.bytes);
+    if (rc != SM_OK) return rc;
+    const char* w = static_cast<const char*>(ws);
+    if (overlap(w, L.bytes, keys, kb) || overlap(w, L.bytes, out_keys, kb) ||
+        (pay && (overlap(w, L.bytes, payloads, pb) || overlap(w, L.bytes, out_payloads, pb))))
+        return fail(SM_ERR_ALIAS, "workspace overlaps the keys or payloads");
+    hipError_t e = sm::launch_sort(dtype, keys, payloads, N, out_keys, out_payloads, run, tile,
+                                   static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "sort launch");
     return SM_OK;
 }
 

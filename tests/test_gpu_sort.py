@@ -1,0 +1,117 @@
+"""GPU parity of the stable merge sort against the CPU oracle (bit-exact),
+and at full size against the definition of a stable sort."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from helpers import dev, flush, host
+
+pytestmark = pytest.mark.gpu
+
+import paper_1202_6575_amd as sm  # noqa: E402
+
+DTYPES = [np.int32, np.uint32, np.uint64]
+
+
+def rand_keys(g, N, alphabet, dtype):
+    """Unsorted keys over an alphabet spread so that signed / unsigned order
+    matters (negative int32, values above 2^31 / 2^63)."""
+    if dtype == np.int32:
+        return g.integers(-alphabet // 2, alphabet - alphabet // 2, size=N).astype(np.int32)
+    if dtype == np.uint32:
+        return (g.integers(0, alphabet, size=N) * ((2 ** 32 - 1) // alphabet)).astype(np.uint32)
+    return g.integers(0, alphabet, size=N).astype(np.uint64) * np.uint64((2 ** 64 - 1) // alphabet)
+
+
+def check_sort(keys, with_pay=True, run=0, in_place=False, **kw):
+    N = len(keys)
+    pay = np.arange(N, dtype=np.uint32)[::-1].copy() if with_pay else None
+    rk, rp = oracle.sort(keys, pay, run or 512)
+    dk = dev(keys)
+    dp = None if pay is None else dev(pay)
+    if in_place:
+        ck, cp = sm.sort(dk, dp, out_keys=dk, out_payloads=dp, run=run, **kw)
+    else:
+        ck, cp = sm.sort(dk, dp, run=run, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ck), rk), "keys differ"
+    if with_pay:
+        assert np.array_equal(host(cp), rp), "payloads differ"
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_sort_sizes(dtype, with_pay):
+    """Ragged sizes around the run length and across several passes."""
+    g = np.random.default_rng(21)
+    for N in [0, 1, 2, 511, 512, 513, 1024, 1500, 4096, 20_001, 131_073]:
+        for alpha in (3, 1 << 30):
+            flush(f"sort dtype={np.dtype(dtype).name} pay={with_pay} N={N} alpha={alpha}")
+            check_sort(rand_keys(g, N, alpha, dtype), with_pay)
+
+
+@pytest.mark.parametrize("run", [256, 512, 1024, 2048])
+def test_sort_run_lengths(run):
+    """Every run length and a tiny merge tile give the same bytes."""
+    g = np.random.default_rng(run)
+    keys = rand_keys(g, 300_007, 100, np.uint32)
+    flush(f"sort run={run}")
+    check_sort(keys, True, run=run)
+    check_sort(keys, True, run=run, tile=64)
+
+
+def test_sort_special_inputs():
+    ar = np.arange(100_000)
+    for keys in [ar.astype(np.int32), ar[::-1].astype(np.int32), np.full(70_000, 5, np.int32),
+                 (ar % 7).astype(np.int32), np.array([np.iinfo(np.int32).max] * 600 +
+                                                      [np.iinfo(np.int32).min] * 600, np.int32)]:
+        flush(f"sort special N={len(keys)}")
+        check_sort(keys, True)
+
+
+def test_sort_in_place():
+    g = np.random.default_rng(4)
+    for N in [700, 5000, 100_000]:      # odd and even numbers of passes
+        flush(f"sort in place N={N}")
+        check_sort(rand_keys(g, N, 50, np.uint64), True, in_place=True)
+        check_sort(rand_keys(g, N, 50, np.int32), False, in_place=True)
+
+
+def test_sort_alias_rejected():
+    k = dev(np.arange(1000, dtype=np.uint32))
+    with pytest.raises(sm.SMError) as e:
+        sm.sort(k[:996], out_keys=k[4:])
+    assert e.value.code in (-1, -3)
+    with pytest.raises(sm.SMError) as e:
+        sm.sort(k, run=300)
+    assert e.value.code == -1
+
+
+@pytest.mark.slow
+def test_config4b_full_size():
+    """N = 2^28 uint32 keys uniform in [0, 2^24), payload = index, runs of
+    512 and 19 merge passes.  With distinct payloads in input order the
+    stable sort is the unique order by (key, payload): the output must be a
+    permutation of the input pairs that is strictly increasing in that order."""
+    N = 1 << 28
+    flush("config4b generate")
+    keys, pay = datagen.sort_input(N, 1 << 24, seed=datagen.BASE_SEED + 5)
+    dk, dp = dev(keys), dev(pay)
+    flush("config4b gpu sort")
+    ck, cp = sm.sort(dk, dp)
+    torch.cuda.synchronize()
+    comp = ck.to(torch.int64) << 32 | cp.to(torch.int64)
+    assert bool((comp[1:] > comp[:-1]).all())
+    # the payloads are a permutation of 0..N-1 and carry their own keys
+    assert bool((torch.sort(cp.to(torch.int64)).values ==
+                 torch.arange(N, device=cp.device)).all())
+    assert torch.equal(dk.to(torch.int64)[cp.to(torch.int64)], ck.to(torch.int64))
+    # sampled windows against the oracle's merge sort of the same input
+    flush("config4b oracle check on a prefix")
+    M = 1 << 20
+    rk, rp = oracle.sort(keys[:M], pay[:M], 512)
+    sub, _ = sm.sort(dev(keys[:M]), dev(pay[:M]))
+    torch.cuda.synchronize()
+    assert np.array_equal(host(sub), rk)
