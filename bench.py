@@ -121,6 +121,10 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare one output with the oracle")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-merge and merge-sort measurements")
+    ap.add_argument("--batch-log2max", type=int, default=15,
+                    help="batched pairs: totals log-uniform in [16, 2^this]")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--pmc-out", default=PMC_FILE)
     args = ap.parse_args()
@@ -248,7 +252,166 @@ def main():
                            "ms": round(copy_ms, 4),
                            "kernel": "elementwise bitwise_not, reads and writes n+m uint32"},
     }
+    if not args.no_extras:
+        del keys, out, ws, xbar, ybar, A, B
+        torch.cuda.empty_cache()
+        res["batched"] = bench_batched(args, gelems)
+        log(f"bench: batched {json.dumps(res['batched'])}")
+        torch.cuda.empty_cache()
+        res["sort"] = bench_sort(args)
+        log(f"bench: sort {json.dumps(res['sort'])}")
     print(json.dumps(res), flush=True)
+
+
+def _events_ms(fn, steps, stream):
+    """Mean ms of fn() over `steps` runs, HIP events on `stream`."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_batched(args, plain_gelems):
+    """65,536 independent pairs, totals L_k log-uniform in [16, 2^15] (about
+    2^28 int32 keys in [0, 2^20)), keys only: the batched merge captured in
+    one graph, the tile chosen by the autotuner, against one stable_merge
+    call per pair on a sample of pairs."""
+    import numpy as np
+    import torch
+    import datagen
+    import datagen.torch_gen as tg
+    import paper_1202_6575_amd as sm
+    from paper_1202_6575_amd import autotune
+
+    count = 65536
+    log(f"bench: batched merge, {count} pairs, totals in [16, 2^{args.batch_log2max}]")
+    n_k, m_k = datagen.batch_lengths(count, 4, args.batch_log2max, seed=datagen.BASE_SEED + 4)
+    keys, offsets, n_a = tg.batched_pairs(n_k, m_k, 0, 1 << 20, seed=datagen.BASE_SEED + 4)
+    total = keys.numel()
+    out = torch.empty_like(keys)
+    stream = torch.cuda.current_stream()
+
+    def valid(t):
+        return sm.batched_workspace_bytes(count, total, torch.int32, False, tile=t) > 0
+
+    wss = {}
+
+    def run(t):
+        if t not in wss:
+            wss[t] = torch.empty(sm.batched_workspace_bytes(count, total, torch.int32, False, tile=t),
+                                 dtype=torch.uint8, device=keys.device)
+        sm.merge_batched(keys, offsets, n_a, out_keys=out, tile=t, workspace=wss[t],
+                         stream=stream)
+
+    tile, tune_ms = autotune.tune("batched", run, torch.int32, False, total, valid=valid,
+                                  use_cache=False)
+    ws = wss[tile]
+    for t in list(wss):
+        if t != tile:
+            del wss[t]
+    run(tile)
+    torch.cuda.synchronize()
+    eager_out = out.clone()
+    # one graph holds the whole launch sequence of the batched merge
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            sm.merge_batched(keys, offsets, n_a, out_keys=out, tile=tile, workspace=ws,
+                             stream=side)
+    torch.cuda.synchronize()
+    out.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    graph_ok = bool(torch.equal(out, eager_out))
+    steps = max(5, args.steps)
+    for _ in range(2):
+        g.replay()
+    graph_ms = _events_ms(g.replay, steps, stream)
+    eager_ms = _events_ms(lambda: run(tile), steps, stream)
+    gel = total / (graph_ms * 1e-3) / 1e9
+    alg = total * 2 * 4
+
+    # one stable_merge call per pair, on a sample of pairs copied to 16-byte
+    # aligned slots (the library requires aligned arrays)
+    g_np = np.random.default_rng(7)
+    sample = np.sort(g_np.choice(count, 2048, replace=False))
+    off_h = offsets.cpu().numpy()
+    na_h = n_a.cpu().numpy()
+    lens = off_h[sample + 1] - off_h[sample]
+    slots = np.zeros(len(sample) + 1, np.int64)
+    np.cumsum((lens + 3) // 4 * 4, out=slots[1:])
+    packed = torch.empty(int(slots[-1]), dtype=torch.int32, device=keys.device)
+    for i, k in enumerate(sample):
+        packed[slots[i]:slots[i] + lens[i]] = keys[off_h[k]:off_h[k + 1]]
+    pout = torch.empty_like(packed)
+    pws = torch.empty(max(sm.workspace_bytes(int(na_h[k]), int(L - na_h[k]), torch.int32)
+                          for k, L in zip(sample, lens)),
+                      dtype=torch.uint8, device=keys.device)
+    views = [(packed[slots[i]:slots[i] + lens[i]], int(na_h[k]), int(lens[i] - na_h[k]),
+              pout[slots[i]:slots[i] + lens[i]]) for i, k in enumerate(sample)]
+
+    def per_pair():
+        for kv, na, mb, ov in views:
+            sm.merge(kv, na, mb, out_keys=ov, workspace=pws, stream=stream)
+
+    per_pair()
+    pp_ms = _events_ms(per_pair, 2, stream)
+    pp_gel = float(lens.sum()) / (pp_ms * 1e-3) / 1e9
+    return {"workload": f"{count} pairs, L_k = floor(2^U), U ~ U[4, {args.batch_log2max}], "
+                        f"m_k = floor(f L_k), int32 keys uniform in [0, 2^20), keys only",
+            "total_elements": total, "Gelem/s": round(gel, 2), "ms": round(graph_ms, 4),
+            "eager_ms": round(eager_ms, 4), "graph_launches_per_step": 1,
+            "graph_replay_matches_eager": graph_ok,
+            "autotune": {"tile": tile, "items_per_lane": 2 * tile // 256,
+                         "ms_by_tile": {str(k): round(v, 4) for k, v in tune_ms.items()}},
+            "roofline": {"bound": "hbm", "achieved": round(alg / (graph_ms * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(alg / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "per_pair_calls": {"pairs_sampled": len(sample), "Gelem/s": round(pp_gel, 3),
+                               "speedup_of_batched": round(gel / pp_gel, 1)},
+            "vs_plain_merge_Gelem/s": round(gel / plain_gelems, 3)}
+
+
+def bench_sort(args):
+    """Stable merge sort of 2^28 (uint32 key uniform in [0, 2^24), uint32
+    index) pairs: runs of 512 formed in LDS, then 19 merge passes."""
+    import torch
+    import datagen
+    import datagen.torch_gen as tg
+    import paper_1202_6575_amd as sm
+
+    N = 1 << 28
+    log("bench: merge sort of 2^28 (key, index) pairs")
+    keys, pay = tg.sort_input(N, 1 << 24, seed=datagen.BASE_SEED + 5)
+    ok, op = torch.empty_like(keys), torch.empty_like(pay)
+    ws = torch.empty(sm.sort_workspace_bytes(N, torch.uint32, True), dtype=torch.uint8,
+                     device=keys.device)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        sm.sort(keys, pay, out_keys=ok, out_payloads=op, workspace=ws, stream=stream)
+
+    run()
+    torch.cuda.synchronize()
+    ok64 = ok.to(torch.int64)
+    sorted_ok = bool((ok64[1:] >= ok64[:-1]).all())
+    del ok64
+    ms = _events_ms(run, 3, stream)
+    passes = 19
+    # run formation + every pass read and write 8 bytes per element
+    alg = N * 8 * 2 * (passes + 1)
+    return {"workload": "N=2^28 uint32 keys uniform in [0, 2^24), uint32 payload = index, "
+                        "runs of 512, 19 merge passes",
+            "Gelem/s": round(N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3),
+            "passes": passes, "output_sorted": sorted_ok,
+            "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1)}
 
 
 if __name__ == "__main__":

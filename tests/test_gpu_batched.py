@@ -66,7 +66,7 @@ def test_batched_mixed_sizes(dtype, with_pay):
     check_batched(keys, offsets, n_a, with_pay)
 
 
-@pytest.mark.parametrize("tile", [1, 7, 64, 1000])
+@pytest.mark.parametrize("tile", [1, 7, 64, 1000, 1536, 3072, 4096])
 def test_batched_tiles(tile):
     """Tiny tiles split nearly every pair into many subproblems."""
     n_k, m_k = datagen.batch_lengths(120, 0, 12, seed=tile)
