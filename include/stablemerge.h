@@ -199,6 +199,113 @@ SM_API int stable_merge_sort(const void *keys, const uint32_t *payloads, int64_t
 SM_API size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_payload,
                                                 const sm_options *opt);
 
+/* ------------------------------------------------------------------------
+ * Learned cross ranks (an addition to the paper).  Steps 1-2 find every
+ * cross rank by binary search.  These calls let a small network predict
+ * where each rank lies and a bounded exponential search finish the job;
+ * the ranks, and so every merge, stay exactly those of the paper.
+ *
+ * The network models the cumulative distribution of a sorted array X:
+ * phi(key) = log2(u + 1) / bits (u the key in unsigned order: int32 with its
+ * sign bit flipped; bits = 32, or 64 for SM_UINT64), h = ReLU(W1 phi + b1)
+ * with 32 hidden units, y = w2 . h + b2 ~ rank / len(X).  Parameters are 97
+ * device floats: W1[0:32], b1[32:64], w2[64:96], b2[96].  All arithmetic is
+ * FP32.  A prediction is clamp(rint(y * len), 0, len).
+ * ------------------------------------------------------------------------ */
+#define SM_MLP_HIDDEN 32
+#define SM_MLP_PARAMS 97
+#define SM_HIST_BINS 65   /* error histogram: bin 32 = exact, 32 +- (1 + floor(log2 |e|)) */
+
+/* Device workspace of sm_mlp_grad for `samples` samples (0 on bad arguments). */
+SM_API size_t sm_mlp_grad_workspace_bytes(int64_t samples);
+
+/*
+ * Forward and backward pass over a sample: grad[97] = d loss / d params and
+ * *loss (optional, may be NULL) for loss = mean over k of (y(keys[k]) -
+ * target[k])^2, with the ReLU derivative taken as 0 at 0.  keys (dtype) and
+ * target (float, normalised ranks) hold `samples` device entries.  The
+ * reduction order is fixed: the same inputs give the same bits.
+ */
+SM_API int sm_mlp_grad(const float *params, const void *keys, const float *target,
+                       int64_t samples, int dtype, float *grad, float *loss,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One Adam step (Kingma and Ba, 2015) in place: m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, params -= lr m / (1 - b1^step) /
+ * (sqrt(v / (1 - b2^step)) + eps).  params, m, v, grad: 97 device floats.
+ */
+SM_API int sm_mlp_adam(float *params, float *m, float *v, const float *grad, int64_t step,
+                       float lr, float beta1, float beta2, float eps, void *stream);
+
+/*
+ * Interpolating knot initialisation from a sorted sample of `samples` query
+ * keys and their targets: hidden unit k is ReLU(phi - c_k) with c_k the
+ * feature of sample i_k = floor((k + 1/2) samples / 32) (W1 = 1, b1 = -c_k),
+ * and the output layer makes the network the piecewise-linear interpolant of
+ * the points (c_k, target[i_k]): b2 = target[i_0], w2[k] = s_k - s_{k-1} with
+ * s_k the slope between knots k and k + 1 (0 if they are closer than 1e-6;
+ * s_31 = 0).  samples = 0 gives all-zero parameters.
+ */
+SM_API int sm_mlp_init(const void *sorted_keys, const float *target, int64_t samples, int dtype,
+                       float *params, void *stream);
+
+/* rhat[i] = clamp(rint(y(keys[i]) * len), 0, len) for q device keys. */
+SM_API int sm_mlp_predict(const float *params, const void *keys, int64_t q, int dtype,
+                          int64_t len, int64_t *rhat, void *stream);
+
+/* Device workspace of sm_rank_model_train (0 on bad arguments). */
+SM_API size_t sm_rank_model_workspace_bytes(int64_t samples, int dtype);
+
+/*
+ * Trains a model of the sorted X[0, len) for queries from the sorted
+ * Q[0, q_len): draws `samples` queries by stratified sampling (one uniform
+ * draw in each of `samples` equal slices of Q, from `seed`), computes their
+ * exact ranks in X by the binary search of Steps 1-2 (rank_high if is_high,
+ * else rank_low), initialises as sm_mlp_init on that sample, then runs
+ * `steps` full-batch
+ * Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error of
+ * the normalised rank, the learning rate decaying from lr to lr / 100 on a
+ * cosine.  Writes params (97 device floats) and, if loss is not NULL, the
+ * final loss (device float; its square root times len is the RMS rank
+ * error on the sample in elements).  len, q_len >= 1.
+ */
+SM_API int sm_rank_model_train(const void *X, int64_t len, const void *Q, int64_t q_len, int dtype,
+                               int is_high, int64_t samples, int64_t steps, float lr,
+                               uint64_t seed, float *params, float *loss,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Exact ranks of q query keys in the sorted X[0, len) from given guesses
+ * (device int64, clamped to [0, len]): rank_low (is_high = 0) or rank_high.
+ * The search probes the guess g, then X[g +- step0], X[g +- 2 step0], ...
+ * away from g until the rank is bracketed (or the array ends), then bisects
+ * the bracket; a step beyond `window` abandons the walk for the plain binary
+ * search over [0, len].  ranks[i] (int64) is always exact; probes[i] (int32:
+ * reads of X) and fallback[i] (int32 0/1) are optional (NULL to skip).
+ * step0 >= 1, 0 <= window <= 2^40.
+ */
+SM_API int stable_merge_rank_search(const void *X, int64_t len, const void *queries, int64_t q,
+                                    int dtype, int is_high, const int64_t *guess, int64_t step0,
+                                    int64_t window, int64_t *ranks, int32_t *probes,
+                                    int32_t *fallback, void *stream);
+
+/*
+ * Steps 1 and 2 with learned starting points: writes exactly what
+ * stable_merge_partition writes (xbar[p_a + 1], ybar[p_b + 1]).  An A block
+ * start x_i < n searches B from model_b's prediction with initial step
+ * step0_a, a B block start searches A from model_a's prediction with
+ * step0_b (both with the given window, as in stable_merge_rank_search).
+ * For every search, hist[bin(predicted - exact)] += 1 (SM_HIST_BINS device
+ * uint64), counters[0] += 1 (searches), counters[1] += fallbacks,
+ * counters[2] += probes (reads of A or B); the caller zeroes them first.
+ */
+SM_API int stable_merge_partition_learned(const void *keys, int64_t n, int64_t m, int64_t p_a,
+                                          int64_t p_b, int dtype, const float *model_b,
+                                          const float *model_a, int64_t step0_a, int64_t step0_b,
+                                          int64_t window, int64_t *xbar, int64_t *ybar,
+                                          uint64_t *hist, uint64_t *counters, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

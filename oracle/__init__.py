@@ -71,7 +71,7 @@ def _load():
         lib.orc_sort.restype = None
         lib.orc_sort.argtypes = [vp, vp, i64, i64, vp, vp, i32]
         lib.orc_gallop.restype = i64
-        lib.orc_gallop.argtypes = [vp, i64, vp, i64, i32, i32, i64, i64,
+        lib.orc_gallop.argtypes = [vp, i64, vp, i64, i32, i32, i64, i64, i64,
                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int)]
         _lib = lib
     return _lib
@@ -197,14 +197,16 @@ def sort(keys, pay=None, run_len: int = 512):
     return keys, pay
 
 
-def gallop(x, X, is_high: bool, guess: int, window: int):
-    """O6: bounded exponential search.  Returns (rank, probes, fallback)."""
+def gallop(x, X, is_high: bool, guess: int, window: int, step0: int = 1):
+    """O6: bounded exponential search from guess with steps step0, 2 step0,
+    4 step0, ... up to window.  Returns (rank, probes, fallback)."""
     X = _c(X)
     xa = np.array([x], dtype=X.dtype)
     probes = ctypes.c_int64(0)
     fb = ctypes.c_int(0)
     r = _load().orc_gallop(_ptr(xa), 0, _ptr(X), len(X), dtype_code(X), int(is_high),
-                           int(guess), int(window), ctypes.byref(probes), ctypes.byref(fb))
+                           int(guess), int(step0), int(window), ctypes.byref(probes),
+                           ctypes.byref(fb))
     return int(r), int(probes.value), bool(fb.value)
 
 

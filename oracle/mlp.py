@@ -87,15 +87,32 @@ def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def init_params(sample_phi_sorted: np.ndarray) -> np.ndarray:
-    """Knot initialisation: unit 32 hinges ReLU(phi - c_k) with c_k the
-    (k + 0.5)/32 quantile of the (sorted) training features, zero output
-    weights and bias."""
+KNOT_MIN_GAP = 1e-6
+
+
+def init_params(sample_phi_sorted: np.ndarray, sample_target: np.ndarray) -> np.ndarray:
+    """Interpolating knot initialisation: hidden unit k is ReLU(phi - c_k)
+    with c_k the feature of sample i_k = floor((k + 1/2) S / 32) of the sorted
+    sample, and the output layer makes the network the piecewise-linear
+    interpolant of the points (c_k, t_k), t_k the target of sample i_k:
+    b2 = t_0, w2[k] = s_k - s_{k-1} with s_k the slope from knot k to knot
+    k + 1 (0 when the two knots are closer than KNOT_MIN_GAP, and s_31 = 0:
+    flat past the last knot)."""
     S = len(sample_phi_sorted)
     p = np.zeros(NPARAM)
-    idx = ((np.arange(HIDDEN) + 0.5) * S / HIDDEN).astype(np.int64)
+    if S == 0:
+        return p
+    idx = np.minimum(((np.arange(HIDDEN) + 0.5) * S / HIDDEN).astype(np.int64), S - 1)
+    c = np.asarray(sample_phi_sorted, dtype=np.float64)[idx]
+    t = np.asarray(sample_target, dtype=np.float64)[idx]
+    slope = np.zeros(HIDDEN)
+    for k in range(HIDDEN - 1):
+        gap = c[k + 1] - c[k]
+        slope[k] = (t[k + 1] - t[k]) / gap if gap > KNOT_MIN_GAP else 0.0
     p[0:32] = 1.0
-    p[32:64] = -sample_phi_sorted[np.minimum(idx, S - 1)] if S else 0.0
+    p[32:64] = -c
+    p[64:96] = slope - np.concatenate([[0.0], slope[:-1]])
+    p[96] = t[0]
     return p
 
 

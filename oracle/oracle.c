@@ -458,13 +458,15 @@ void orc_sort(void *keys, uint32_t *pay, int64_t N, int64_t run_len,
  * x = XA[xi] in X[0, len), starting from the guess g (clamped to [0, len]).
  * Let pred(t) be "X[t] < x" (low) or "X[t] <= x" (high); the rank is the
  * number of t with pred(t) true.  The search probes g, then moves away from
- * g in steps of 1, 2, 4, ... until the rank is bracketed, then binary
- * searches the bracket.  If a step larger than window would be needed, it
- * gives up and runs the plain binary search over [0, len] instead
- * (*fallback = 1).  *probes counts every element of X that is read.
+ * g in steps of step0, 2 step0, 4 step0, ... until the rank is bracketed,
+ * then binary searches the bracket.  If a step larger than window would be
+ * needed, it gives up and runs the plain binary search over [0, len]
+ * instead (*fallback = 1).  *probes counts every element of X that is read.
+ * step0 >= 1 (the initial step is a free choice of the search: a predictor
+ * whose typical error is e starts near e instead of 1).
  */
 int64_t orc_gallop(const void *XA, int64_t xi, const void *X, int64_t len, int dtype,
-                   int is_high, int64_t g, int64_t window,
+                   int is_high, int64_t g, int64_t step0, int64_t window,
                    int64_t *probes, int *fallback)
 {
     int64_t lo, hi, np = 0;
@@ -474,7 +476,7 @@ int64_t orc_gallop(const void *XA, int64_t xi, const void *X, int64_t len, int d
     if (g > len) g = len;
     if (g < len && PRED(g)) {
         /* rank > g: move right */
-        int64_t d = 1;
+        int64_t d = step0 < 1 ? 1 : step0;
         lo = g + 1;
         for (;;) {
             if (d > window) goto full;
@@ -486,7 +488,7 @@ int64_t orc_gallop(const void *XA, int64_t xi, const void *X, int64_t len, int d
         }
     } else {
         /* rank <= g: move left */
-        int64_t d = 1;
+        int64_t d = step0 < 1 ? 1 : step0;
         hi = g;
         for (;;) {
             if (d > window) goto full;

@@ -19,6 +19,7 @@
 #include "sm_device.h"
 #include "sm_launch.h"
 #include "sm_sort.h"
+#include "sm_learned.h"
 
 namespace {
 
@@ -163,7 +164,14 @@ int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t*
                     void* out_keys, uint32_t* out_payloads, char* tail, hipStream_t st) {
     sm::PieceDesc* desc = reinterpret_cast<sm::PieceDesc*>(tail);
     const int64_t P = pl.p_a + pl.p_b;
-    hipError_t e = sm::launch_cases(n, m, pl.p_a, pl.p_b, xbar, ybar, desc, st);
+    hipError_t e;
+    if (!pl.hier && pl.cap <= sm::kFineCap) {
+        e = sm::launch_fine_merge(dtype, keys, payloads, n, m, pl.p_a, pl.p_b, xbar, ybar, out_keys,
+                                  out_payloads, st);
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+        return SM_OK;
+    }
+    e = sm::launch_cases(n, m, pl.p_a, pl.p_b, xbar, ybar, desc, st);
     if (e != hipSuccess) return hip_fail(e, "cases launch");
     if (!pl.hier)
         e = sm::launch_merge_desc(dtype, keys, payloads, n + m, out_keys, out_payloads, n + m, desc,
@@ -397,6 +405,112 @@ int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, voi
                                    static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "sort launch");
     return SM_OK;
+}
+
+size_t sm_mlp_grad_workspace_bytes(int64_t samples) {
+    return samples < 0 ? 0 : sm::mlp_grad_ws_bytes(samples);
+}
+
+int sm_mlp_grad(const float* params, const void* keys, const float* target, int64_t samples,
+                int dtype, float* grad, float* loss, void* ws, size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (samples < 1 || samples > (1ll << 34)) return fail(SM_ERR_ARG, "samples must be in [1, 2^34]");
+    if (!params || !keys || !target || !grad) return fail(SM_ERR_ARG, "NULL pointer");
+    int rc = check_ws(ws, ws_bytes, sm::mlp_grad_ws_bytes(samples));
+    if (rc != SM_OK) return rc;
+    hipError_t e = sm::launch_mlp_grad(dtype, params, keys, target, samples, grad, loss, ws,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "mlp grad launch");
+}
+
+int sm_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step, float lr,
+                float beta1, float beta2, float eps, void* stream) {
+    if (!params || !m || !v || !grad) return fail(SM_ERR_ARG, "NULL pointer");
+    if (step < 1) return fail(SM_ERR_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
+        return fail(SM_ERR_ARG, "need 0 <= beta1, beta2 < 1 and eps > 0");
+    hipError_t e = sm::launch_mlp_adam(params, m, v, grad, step, lr, beta1, beta2, eps,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "adam launch");
+}
+
+int sm_mlp_init(const void* sorted_keys, const float* target, int64_t samples, int dtype,
+                float* params, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (samples < 0 || (samples > 0 && (!sorted_keys || !target)) || !params)
+        return fail(SM_ERR_ARG, "bad sample or NULL pointer");
+    hipError_t e = sm::launch_mlp_init(dtype, sorted_keys, target, samples, params,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "init launch");
+}
+
+int sm_mlp_predict(const float* params, const void* keys, int64_t q, int dtype, int64_t len,
+                   int64_t* rhat, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (q < 0 || len < 0 || len > (1ll << 40)) return fail(SM_ERR_ARG, "bad sizes");
+    if (q > 0 && (!params || !keys || !rhat)) return fail(SM_ERR_ARG, "NULL pointer");
+    hipError_t e = sm::launch_mlp_predict(dtype, params, keys, q, len, rhat,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "predict launch");
+}
+
+size_t sm_rank_model_workspace_bytes(int64_t samples, int dtype) {
+    if (!dtype_ok(dtype) || samples < 1 || samples > (1ll << 34)) return 0;
+    return sm::rank_model_layout(samples, dtype).bytes;
+}
+
+int sm_rank_model_train(const void* X, int64_t len, const void* Q, int64_t q_len, int dtype,
+                        int is_high, int64_t samples, int64_t steps, float lr, uint64_t seed,
+                        float* params, float* loss, void* ws, size_t ws_bytes, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (len < 1 || q_len < 1 || len > (1ll << 40) || q_len > (1ll << 40))
+        return fail(SM_ERR_ARG, "the searched and the query arrays must be non-empty");
+    if (samples < 1 || samples > (1ll << 34) || steps < 0 || !(lr > 0.0f))
+        return fail(SM_ERR_ARG, "samples >= 1, steps >= 0 and lr > 0 required");
+    if (!X || !Q || !params) return fail(SM_ERR_ARG, "NULL pointer");
+    const sm::RankModelLayout L = sm::rank_model_layout(samples, dtype);
+    int rc = check_ws(ws, ws_bytes, L.bytes);
+    if (rc != SM_OK) return rc;
+    hipError_t e = sm::launch_rank_model_train(dtype, X, len, Q, q_len, is_high != 0, samples, steps,
+                                               lr, seed, params, loss, static_cast<char*>(ws), L,
+                                               static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "training launch");
+}
+
+int stable_merge_rank_search(const void* X, int64_t len, const void* queries, int64_t q, int dtype,
+                             int is_high, const int64_t* guess, int64_t step0, int64_t window,
+                             int64_t* ranks, int32_t* probes, int32_t* fallback, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (len < 0 || q < 0 || len > (1ll << 40)) return fail(SM_ERR_ARG, "bad sizes");
+    if (step0 < 1 || window < 0 || window > (1ll << 40))
+        return fail(SM_ERR_ARG, "step0 >= 1 and 0 <= window <= 2^40 required");
+    if (q > 0 && (!queries || !guess || !ranks || (len > 0 && !X)))
+        return fail(SM_ERR_ARG, "NULL pointer");
+    hipError_t e = sm::launch_rank_search(dtype, X, len, queries, q, is_high != 0, guess, step0,
+                                          window, ranks, probes, fallback,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "search launch");
+}
+
+int stable_merge_partition_learned(const void* keys, int64_t n, int64_t m, int64_t p_a,
+                                   int64_t p_b, int dtype, const float* model_b,
+                                   const float* model_a, int64_t step0_a, int64_t step0_b,
+                                   int64_t window, int64_t* xbar, int64_t* ybar, uint64_t* hist,
+                                   uint64_t* counters, void* stream) {
+    int rc = check_sizes(n, m, dtype);
+    if (rc != SM_OK) return rc;
+    if (p_a < 1 || p_b < 1 || p_a + p_b > (1ll << 40)) return fail(SM_ERR_ARG, "bad block counts");
+    if (step0_a < 1 || step0_b < 1 || window < 0 || window > (1ll << 40))
+        return fail(SM_ERR_ARG, "step0 >= 1 and 0 <= window <= 2^40 required");
+    if (!xbar || !ybar || !hist || !counters || !model_a || !model_b)
+        return fail(SM_ERR_ARG, "NULL pointer");
+    if (n + m > 0 && !keys) return fail(SM_ERR_ARG, "keys must not be NULL");
+    if (reinterpret_cast<uintptr_t>(keys) % key_bytes(dtype))
+        return fail(SM_ERR_ARG, "keys misaligned");
+    hipError_t e = sm::launch_learned_partition(dtype, keys, n, m, p_a, p_b, model_b, model_a,
+                                                step0_a, step0_b, window, xbar, ybar, hist,
+                                                counters, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SM_OK : hip_fail(e, "learned partition launch");
 }
 
 }  // extern "C"

@@ -40,6 +40,14 @@ hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, i
                              const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
                              hipStream_t st);
 
+// Steps 3-4 plus the merges for small blocks: one lane per subproblem, no
+// descriptors (subproblems of at most kFineCap elements).
+hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n,
+                            int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
+                            const int64_t* ybar, void* out_keys, uint32_t* out_pay,
+                            hipStream_t st);
+constexpr uint32_t kFineCap = 64;
+
 // Subproblem capacity (elements) that one merge workgroup can stage for a
 // key type, in the register-pipelined kernel at the default tile.
 uint32_t merge_cap_for_tile(int32_t tile);

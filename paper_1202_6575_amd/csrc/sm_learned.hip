@@ -1,0 +1,520 @@
+// sm_learned.hip -- learned cross ranks (an addition to the paper's Steps 1-2).
+//
+// The paper finds every cross rank by binary search (Section 2, Steps 1-2).
+// Here a 1 -> 32 (ReLU) -> 1 network models the cumulative distribution of
+// the array searched, mapping a key to its normalised rank; its prediction
+// is the starting point of a bounded exponential search that ends at the
+// exact rank_low / rank_high, with the plain binary search as the fallback
+// when the search would have to move farther than a window.  The network
+// only decides where the search starts, never the result.
+//
+// Kernels: training-set sampling (exact ranks by the method's own binary
+// search), knot initialisation, forward + backward over a sample with a
+// fixed-order reduction (bitwise reproducible), Adam, prediction, the
+// bounded search from given guesses, and the learned partition (Steps 1-2
+// with predicted starting points, an error histogram and fallback / probe
+// counters).
+#include "sm_device.h"
+#include "sm_launch.h"
+#include "sm_learned.h"
+
+namespace sm {
+
+namespace {
+
+constexpr int H = kMlpHidden;
+constexpr int NP = kMlpParams;
+constexpr int NACC = NP + 1;  // the gradient and the squared-error sum
+constexpr int kGradThreads = 256;
+
+// phi(key) = log2(u + 1) / bits, u the order-preserving unsigned form of the key.
+__device__ __forceinline__ float feature(int32_t x) {
+    const uint32_t u = (uint32_t)x ^ 0x80000000u;
+    return log2f((float)u + 1.0f) * (1.0f / 32.0f);
+}
+__device__ __forceinline__ float feature(uint32_t x) {
+    return log2f((float)x + 1.0f) * (1.0f / 32.0f);
+}
+__device__ __forceinline__ float feature(uint64_t x) {
+    return log2f((float)x + 1.0f) * (1.0f / 64.0f);
+}
+
+// y = b2 + sum_k w2[k] * ReLU(W1[k] * phi + b1[k]); parameters W1[0:32],
+// b1[32:64], w2[64:96], b2[96].
+__device__ __forceinline__ float mlp_forward(const float* __restrict__ P, float phi) {
+    float y = P[3 * H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const float h = fmaxf(fmaf(P[k], phi, P[H + k]), 0.0f);
+        y = fmaf(P[2 * H + k], h, y);
+    }
+    return y;
+}
+
+// Predicted rank clamp(rint(y * len), 0, len).
+__device__ __forceinline__ int64_t predict(const float* __restrict__ P, float phi, int64_t len) {
+    const double r = rint((double)mlp_forward(P, phi) * (double)len);
+    return r <= 0.0 ? 0 : (r >= (double)len ? len : (int64_t)r);
+}
+
+// Bounded exponential search for the rank of x in X[0, len): probe the
+// guess g, then step away from it by step0, 2 step0, 4 step0, ... until the
+// rank is bracketed (or the array ends), then bisect the bracket.  A step
+// beyond `window` abandons the walk for the binary search over [0, len].
+// Low: pred(t) = X[t] < x (rank_low); high: pred(t) = X[t] <= x (rank_high);
+// the rank is the number of t with pred(t).  `probes` counts reads of X.
+template <typename K, bool HIGH>
+__device__ __forceinline__ int64_t bounded_search(const K* __restrict__ X, int64_t len, K x,
+                                                  int64_t g, int64_t step0, int64_t window,
+                                                  int& probes, bool& fell_back) {
+    int np = 0;
+    auto pred = [&](int64_t t) {
+        ++np;
+        const K v = X[t];
+        return HIGH ? !(x < v) : (v < x);
+    };
+    g = g < 0 ? 0 : (g > len ? len : g);
+    int64_t lo = 0, hi = len;
+    bool fb = false;
+    int64_t d = step0 < 1 ? 1 : step0;
+    if (g < len && pred(g)) {
+        lo = g + 1;  // the rank is above g
+        for (;;) {
+            if (d > window) { fb = true; break; }
+            const int64_t t = g + d;
+            if (t >= len) { hi = len; break; }
+            if (!pred(t)) { hi = t; break; }
+            lo = t + 1;
+            d <<= 1;
+        }
+    } else {
+        hi = g;  // the rank is at most g
+        for (;;) {
+            if (d > window) { fb = true; break; }
+            const int64_t t = g - d;
+            if (t < 0) { lo = 0; break; }
+            if (pred(t)) { lo = t + 1; break; }
+            hi = t;
+            d <<= 1;
+        }
+    }
+    if (fb) {
+        lo = 0;
+        hi = len;
+    }
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (pred(mid)) lo = mid + 1;
+        else hi = mid;
+    }
+    probes = np;
+    fell_back = fb;
+    return lo;
+}
+
+// Histogram bin of a rank error e = predicted - exact: 32 for 0, 32 + 1 +
+// floor(log2 e) for e > 0 and 32 - 1 - floor(log2 -e) for e < 0, clipped
+// to [0, 64].
+__device__ __forceinline__ int error_bin(int64_t e) {
+    if (e == 0) return kHistCenter;
+    const uint64_t a = (uint64_t)(e < 0 ? -e : e);
+    const int lg = 63 - __clzll((long long)a);
+    int b = e > 0 ? kHistCenter + 1 + lg : kHistCenter - 1 - lg;
+    return b < 0 ? 0 : (b > kHistBins - 1 ? kHistBins - 1 : b);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Training set: S queries drawn from the sorted Q by stratified sampling
+// (sample k uniform in the k-th of S equal slices, so the sample is sorted),
+// exact ranks in X by the plain binary search, targets r / len.
+template <typename K>
+__global__ __launch_bounds__(256) void rank_sample_kernel(const K* __restrict__ X, int64_t len,
+                                                          const K* __restrict__ Q, int64_t q_len,
+                                                          int is_high, int64_t S, uint64_t seed,
+                                                          K* __restrict__ skeys,
+                                                          float* __restrict__ target) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double u = (double)(splitmix64(seed ^ (0x5851f42d4c957f2dull * (uint64_t)(k + 1))) >> 11) *
+                         (1.0 / 9007199254740992.0);
+        int64_t idx = (int64_t)(((double)k + u) * (double)q_len / (double)S);
+        idx = idx < 0 ? 0 : (idx >= q_len ? q_len - 1 : idx);
+        const K x = Q[idx];
+        const int64_t r = is_high ? rank_high<K, int64_t>(X, len, x) : rank_low<K, int64_t>(X, len, x);
+        skeys[k] = x;
+        target[k] = (float)((double)r / (double)len);
+    }
+}
+
+// Interpolating knot initialisation: hinge k at c_k = phi of sample
+// i_k = floor((k + 1/2) S / 32) of the sorted sample (W1 = 1, b1 = -c_k), and
+// an output layer that makes the network the piecewise-linear interpolant of
+// the points (c_k, t_k): b2 = t_0, w2[k] = s_k - s_{k-1}, s_k the slope from
+// knot k to knot k + 1 (0 for knots closer than 1e-6, and s_31 = 0).
+template <typename K>
+__global__ void mlp_init_kernel(const K* __restrict__ sorted_keys, const float* __restrict__ target,
+                                int64_t S, float* __restrict__ P) {
+    if (threadIdx.x != 0) return;
+    if (S <= 0) {
+        for (int j = 0; j < NP; ++j) P[j] = 0.0f;
+        return;
+    }
+    float c_prev = 0.0f, t_prev = 0.0f, s_prev = 0.0f;
+    for (int k = 0; k < H; ++k) {
+        int64_t idx = (int64_t)(((double)k + 0.5) * (double)S / (double)H);
+        idx = idx >= S ? S - 1 : idx;
+        const float c = feature(sorted_keys[idx]);
+        const float t = target[idx];
+        P[k] = 1.0f;
+        P[H + k] = -c;
+        if (k == 0) {
+            P[3 * H] = t;
+        } else {
+            const float gap = c - c_prev;
+            const float s = gap > 1e-6f ? (t - t_prev) / gap : 0.0f;
+            P[2 * H + k - 1] = s - s_prev;
+            s_prev = s;
+        }
+        c_prev = c;
+        t_prev = t;
+    }
+    P[2 * H + H - 1] = -s_prev;  // s_31 = 0: flat past the last knot
+}
+
+// Deterministic wave sum: butterfly over the 64 lanes in a fixed order.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Partial sums of d(loss * S)/dparams and of the squared errors over the
+// samples of one block: dy = 2 (y - t); dw2_k += dy h_k; db2 += dy;
+// dW1_k += dy w2_k [pre_k > 0] phi; db1_k += dy w2_k [pre_k > 0].
+// Sample k goes to block k / per_block, thread (k % per_block) % 256: a
+// fixed assignment and a fixed reduction tree, so the sums are bitwise
+// reproducible.
+template <typename K>
+__global__ __launch_bounds__(kGradThreads) void mlp_grad_kernel(const float* __restrict__ P,
+                                                                const K* __restrict__ keys,
+                                                                const float* __restrict__ target,
+                                                                int64_t S, int64_t per_block,
+                                                                float* __restrict__ partial) {
+    __shared__ float red[kGradThreads / 64][NACC];
+    float acc[NACC];
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) acc[j] = 0.0f;
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = b0 + per_block < S ? b0 + per_block : S;
+    for (int64_t k = b0 + threadIdx.x; k < b1; k += kGradThreads) {
+        const float phi = feature(keys[k]);
+        float pre[H];
+        float y = P[3 * H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            pre[j] = fmaf(P[j], phi, P[H + j]);
+            y = fmaf(P[2 * H + j], fmaxf(pre[j], 0.0f), y);
+        }
+        const float d = y - target[k];
+        const float dy = 2.0f * d;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const float h = fmaxf(pre[j], 0.0f);
+            acc[2 * H + j] = fmaf(dy, h, acc[2 * H + j]);
+            const float dh = pre[j] > 0.0f ? dy * P[2 * H + j] : 0.0f;
+            acc[j] = fmaf(dh, phi, acc[j]);
+            acc[H + j] += dh;
+        }
+        acc[3 * H] += dy;
+        acc[NP] = fmaf(d, d, acc[NP]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) {
+        const float s = wave_sum(acc[j]);
+        if (lane == 0) red[wave][j] = s;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < NACC; j += kGradThreads) {
+        float s = red[0][j];
+#pragma unroll
+        for (int w = 1; w < kGradThreads / 64; ++w) s += red[w][j];
+        partial[(int64_t)blockIdx.x * NACC + j] = s;
+    }
+}
+
+// grad[j] = (sum over blocks, in block order) / S; loss = squared-error sum / S.
+__global__ void mlp_grad_reduce_kernel(const float* __restrict__ partial, int64_t blocks,
+                                       int64_t S, float* __restrict__ grad,
+                                       float* __restrict__ loss) {
+    const int j = threadIdx.x;
+    if (j >= NACC) return;
+    float s = 0.0f;
+    for (int64_t b = 0; b < blocks; ++b) s += partial[b * NACC + j];
+    const float v = S > 0 ? s / (float)S : 0.0f;
+    if (j < NP) grad[j] = v;
+    else if (loss) *loss = v;
+}
+
+// Adam (Kingma and Ba, 2015) with bias correction factors c1 = 1 / (1 - b1^t),
+// c2 = 1 / (1 - b2^t) computed by the host.
+__global__ void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ M, float* __restrict__ V,
+                                const float* __restrict__ G, float lr, float b1, float b2,
+                                float eps, float c1, float c2) {
+    const int j = threadIdx.x;
+    if (j >= NP) return;
+    const float g = G[j];
+    const float m = b1 * M[j] + (1.0f - b1) * g;
+    const float v = b2 * V[j] + (1.0f - b2) * g * g;
+    M[j] = m;
+    V[j] = v;
+    P[j] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ p, int n, float v) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void mlp_predict_kernel(const float* __restrict__ P,
+                                                          const K* __restrict__ keys, int64_t q,
+                                                          int64_t len, int64_t* __restrict__ rhat) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
+         i += (int64_t)gridDim.x * blockDim.x)
+        rhat[i] = predict(P, feature(keys[i]), len);
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void rank_search_kernel(
+    const K* __restrict__ X, int64_t len, const K* __restrict__ Qk, int64_t q, int is_high,
+    const int64_t* __restrict__ guess, int64_t step0, int64_t window, int64_t* __restrict__ ranks,
+    int32_t* __restrict__ probes, int32_t* __restrict__ fallback) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int np;
+        bool fb;
+        const int64_t r = is_high
+                              ? bounded_search<K, true>(X, len, Qk[i], guess[i], step0, window, np, fb)
+                              : bounded_search<K, false>(X, len, Qk[i], guess[i], step0, window, np, fb);
+        ranks[i] = r;
+        if (probes) probes[i] = np;
+        if (fallback) fallback[i] = fb ? 1 : 0;
+    }
+}
+
+// Steps 1-2 with predicted starting points: the same xbar / ybar as the
+// plain partition.  Thread t <= p_a handles A's block start x_t (rank_low in
+// B, network model_b), the others B's block starts (rank_high in A,
+// network model_a).  Per workgroup an LDS histogram of predicted - exact
+// and counts of searches, fallbacks and probes, added to the global ones.
+template <typename K>
+__global__ __launch_bounds__(256) void learned_partition_kernel(
+    const K* __restrict__ keys, int64_t n, int64_t m, int64_t p_a, int64_t p_b,
+    const float* __restrict__ model_b, const float* __restrict__ model_a, int64_t step0_a,
+    int64_t step0_b, int64_t window, int64_t* __restrict__ xbar, int64_t* __restrict__ ybar,
+    unsigned long long* __restrict__ hist, unsigned long long* __restrict__ counters) {
+    __shared__ unsigned int sh[kHistBins];
+    __shared__ unsigned long long sc[3];
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) sh[i] = 0;
+    if (threadIdx.x < 3) sc[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const K* A = keys;
+    const K* B = keys + n;
+    bool searched = false, fb = false;
+    int np = 0;
+    int64_t err = 0;
+    if (t <= p_a) {
+        const int64_t xi = Blocks<int64_t>(n, p_a).start(t);
+        int64_t r = m;
+        if (xi < n) {
+            const K x = A[xi];
+            const int64_t g = predict(model_b, feature(x), m);
+            r = bounded_search<K, false>(B, m, x, g, step0_a, window, np, fb);
+            err = g - r;
+            searched = true;
+        }
+        xbar[t] = r;
+    } else if (t <= p_a + 1 + p_b) {
+        const int64_t j = t - (p_a + 1);
+        const int64_t yj = Blocks<int64_t>(m, p_b).start(j);
+        int64_t r = n;
+        if (yj < m) {
+            const K y = B[yj];
+            const int64_t g = predict(model_a, feature(y), n);
+            r = bounded_search<K, true>(A, n, y, g, step0_b, window, np, fb);
+            err = g - r;
+            searched = true;
+        }
+        ybar[j] = r;
+    }
+    if (searched) {
+        atomicAdd(&sh[error_bin(err)], 1u);
+        atomicAdd(&sc[0], 1ull);
+        if (fb) atomicAdd(&sc[1], 1ull);
+        atomicAdd(&sc[2], (unsigned long long)np);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+        if (sh[i]) atomicAdd(&hist[i], (unsigned long long)sh[i]);
+    if (threadIdx.x < 3 && sc[threadIdx.x]) atomicAdd(&counters[threadIdx.x], sc[threadIdx.x]);
+}
+
+template <typename F>
+void with_key(int dtype, F&& f) {
+    if (dtype == 0) f((int32_t)0);
+    else if (dtype == 1) f((uint32_t)0);
+    else f((uint64_t)0);
+}
+
+unsigned grid_for(int64_t items, int64_t cap_blocks) {
+    int64_t g = (items + 255) / 256;
+    if (g > cap_blocks) g = cap_blocks;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int64_t mlp_grad_blocks(int64_t S) {
+    // about 16 samples per thread, at most 2048 blocks
+    int64_t blocks = (S + kGradThreads * 16 - 1) / (kGradThreads * 16);
+    if (blocks > 2048) blocks = 2048;
+    return blocks < 1 ? 1 : blocks;
+}
+
+size_t mlp_grad_ws_bytes(int64_t S) { return align256((size_t)mlp_grad_blocks(S) * NACC * 4); }
+
+hipError_t launch_mlp_grad(int dtype, const float* P, const void* keys, const float* target,
+                           int64_t S, float* grad, float* loss, void* ws, hipStream_t st) {
+    const int64_t blocks = mlp_grad_blocks(S);
+    const int64_t per_block = (S + blocks - 1) / blocks;
+    float* partial = static_cast<float*>(ws);
+    with_key(dtype, [&](auto z) {
+        using K = decltype(z);
+        mlp_grad_kernel<K><<<(unsigned)blocks, kGradThreads, 0, st>>>(
+            P, static_cast<const K*>(keys), target, S, per_block > 0 ? per_block : 1, partial);
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    mlp_grad_reduce_kernel<<<1, 128, 0, st>>>(partial, blocks, S, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* P, float* M, float* V, const float* G, int64_t step, float lr,
+                           float b1, float b2, float eps, hipStream_t st) {
+    const double c1 = 1.0 / (1.0 - pow((double)b1, (double)step));
+    const double c2 = 1.0 / (1.0 - pow((double)b2, (double)step));
+    mlp_adam_kernel<<<1, 128, 0, st>>>(P, M, V, G, lr, b1, b2, eps, (float)c1, (float)c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(int dtype, const void* sorted_keys, const float* target, int64_t S,
+                           float* P, hipStream_t st) {
+    with_key(dtype, [&](auto z) {
+        using K = decltype(z);
+        mlp_init_kernel<K><<<1, 64, 0, st>>>(static_cast<const K*>(sorted_keys), target, S, P);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_predict(int dtype, const float* P, const void* keys, int64_t q, int64_t len,
+                              int64_t* rhat, hipStream_t st) {
+    if (q <= 0) return hipSuccess;
+    with_key(dtype, [&](auto z) {
+        using K = decltype(z);
+        mlp_predict_kernel<K><<<grid_for(q, 8192), 256, 0, st>>>(P, static_cast<const K*>(keys), q,
+                                                                  len, rhat);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_search(int dtype, const void* X, int64_t len, const void* queries, int64_t q,
+                              int is_high, const int64_t* guess, int64_t step0, int64_t window,
+                              int64_t* ranks, int32_t* probes, int32_t* fallback, hipStream_t st) {
+    if (q <= 0) return hipSuccess;
+    with_key(dtype, [&](auto z) {
+        using K = decltype(z);
+        rank_search_kernel<K><<<grid_for(q, 8192), 256, 0, st>>>(
+            static_cast<const K*>(X), len, static_cast<const K*>(queries), q, is_high, guess, step0,
+            window, ranks, probes, fallback);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_partition(int dtype, const void* keys, int64_t n, int64_t m, int64_t p_a,
+                                    int64_t p_b, const float* model_b, const float* model_a,
+                                    int64_t step0_a, int64_t step0_b, int64_t window, int64_t* xbar,
+                                    int64_t* ybar, uint64_t* hist, uint64_t* counters,
+                                    hipStream_t st) {
+    const int64_t threads = p_a + p_b + 2;
+    const unsigned grid = (unsigned)((threads + 255) / 256);
+    with_key(dtype, [&](auto z) {
+        using K = decltype(z);
+        learned_partition_kernel<K><<<grid, 256, 0, st>>>(
+            static_cast<const K*>(keys), n, m, p_a, p_b, model_b, model_a, step0_a, step0_b, window,
+            xbar, ybar, reinterpret_cast<unsigned long long*>(hist),
+            reinterpret_cast<unsigned long long*>(counters));
+    });
+    return hipGetLastError();
+}
+
+RankModelLayout rank_model_layout(int64_t S, int dtype) {
+    RankModelLayout L;
+    const size_t kb = dtype == 2 ? 8 : 4;
+    size_t off = 0;
+    L.off_keys = off; off += align256((size_t)S * kb);
+    L.off_target = off; off += align256((size_t)S * 4);
+    L.off_partial = off; off += mlp_grad_ws_bytes(S);
+    L.off_grad = off; off += 512;
+    L.off_m = off; off += 512;
+    L.off_v = off; off += 512;
+    L.bytes = off;
+    return L;
+}
+
+hipError_t launch_rank_model_train(int dtype, const void* X, int64_t len, const void* Q,
+                                   int64_t q_len, int is_high, int64_t S, int64_t steps, float lr,
+                                   uint64_t seed, float* P, float* loss, char* ws,
+                                   const RankModelLayout& L, hipStream_t st) {
+    void* skeys = ws + L.off_keys;
+    float* target = reinterpret_cast<float*>(ws + L.off_target);
+    float* partial = reinterpret_cast<float*>(ws + L.off_partial);
+    float* grad = reinterpret_cast<float*>(ws + L.off_grad);
+    float* M = reinterpret_cast<float*>(ws + L.off_m);
+    float* V = reinterpret_cast<float*>(ws + L.off_v);
+    with_key(dtype, [&](auto z) {
+        using K = decltype(z);
+        rank_sample_kernel<K><<<grid_for(S, 4096), 256, 0, st>>>(
+            static_cast<const K*>(X), len, static_cast<const K*>(Q), q_len, is_high, S, seed,
+            static_cast<K*>(skeys), target);
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_mlp_init(dtype, skeys, target, S, P, st)) != hipSuccess) return e;
+    fill_f32_kernel<<<1, 128, 0, st>>>(M, NP, 0.0f);
+    fill_f32_kernel<<<1, 128, 0, st>>>(V, NP, 0.0f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // cosine decay from lr to lr / 100 over the steps
+    const double lr_min = lr / 100.0;
+    for (int64_t t = 1; t <= steps; ++t) {
+        const double c = 0.5 * (1.0 + cos(3.14159265358979323846 * (double)(t - 1) / (double)steps));
+        const float lr_t = (float)(lr_min + (lr - lr_min) * c);
+        if ((e = launch_mlp_grad(dtype, P, skeys, target, S, grad, nullptr, partial, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = launch_mlp_adam(P, M, V, grad, t, lr_t, 0.9f, 0.999f, 1e-8f, st)) != hipSuccess)
+            return e;
+    }
+    // loss of the final parameters
+    return launch_mlp_grad(dtype, P, skeys, target, S, grad, loss, partial, st);
+}
+
+}  // namespace sm

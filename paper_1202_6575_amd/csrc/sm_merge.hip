@@ -136,6 +136,48 @@ __global__ __launch_bounds__(L) void merge_direct_kernel(
     write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
 }
 
+// Steps 3-4 for partitions into small blocks (a subproblem of at most a few
+// dozen elements): one lane per subproblem picks its case from xbar / ybar
+// and merges straight from global memory with the stable two-pointer rule
+// (B first only when strictly smaller), with no descriptor in between.
+template <typename K, bool PAY>
+__global__ __launch_bounds__(256) void fine_merge_kernel(const K* __restrict__ keys,
+                                                         const uint32_t* __restrict__ pay, int64_t n,
+                                                         int64_t m, int64_t p_a, int64_t p_b,
+                                                         const int64_t* __restrict__ xbar,
+                                                         const int64_t* __restrict__ ybar,
+                                                         K* __restrict__ out,
+                                                         uint32_t* __restrict__ out_pay) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= p_a + p_b) return;
+    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
+    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
+                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
+    if (!(0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= n && 0 <= pc.b_lo &&
+          pc.b_lo <= pc.b_hi && pc.b_hi <= m))
+        return;  // cannot happen for cross ranks of sorted inputs; never write outside C
+    const K* A = keys;
+    const K* B = keys + n;
+    int64_t ia = pc.a_lo, ib = pc.b_lo, o = pc.a_lo + pc.b_lo;
+    while (ia < pc.a_hi && ib < pc.b_hi) {
+        const K ka = A[ia], kb = B[ib];
+        const bool tb = kb < ka;
+        out[o] = tb ? kb : ka;
+        if (PAY) out_pay[o] = tb ? pay[n + ib] : pay[ia];
+        ib += tb;
+        ia += !tb;
+        ++o;
+    }
+    for (; ia < pc.a_hi; ++ia, ++o) {
+        out[o] = A[ia];
+        if (PAY) out_pay[o] = pay[ia];
+    }
+    for (; ib < pc.b_hi; ++ib, ++o) {
+        out[o] = B[ib];
+        if (PAY) out_pay[o] = pay[n + ib];
+    }
+}
+
 template <typename K>
 __global__ __launch_bounds__(256) void validate_kernel(const K* __restrict__ keys, int64_t n,
                                                        int64_t m, int* flag) {
@@ -289,6 +331,27 @@ hipError_t launch_merge(int dtype, const void* keys, const uint32_t* pay, int64_
     if (e != hipSuccess) return e;
     return launch_merge_desc(dtype, keys, pay, n + m, out_keys, out_pay, n + m, desc, p_a + p_b,
                              nullptr, cap, st);
+}
+
+hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n,
+                            int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
+                            const int64_t* ybar, void* out_keys, uint32_t* out_pay,
+                            hipStream_t st) {
+    const int64_t P = p_a + p_b;
+    if (P <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((P + 255) / 256);
+    with_dtype(dtype, [&](auto z) {
+        using K = decltype(z);
+        if (pay)
+            fine_merge_kernel<K, true><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), pay, n, m,
+                                                             p_a, p_b, xbar, ybar,
+                                                             static_cast<K*>(out_keys), out_pay);
+        else
+            fine_merge_kernel<K, false><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), nullptr,
+                                                              n, m, p_a, p_b, xbar, ybar,
+                                                              static_cast<K*>(out_keys), nullptr);
+    });
+    return hipGetLastError();
 }
 
 hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, int* flag,

@@ -1,0 +1,154 @@
+"""Learned cross ranks: Python binding of the rank-model entry points of
+libstablemerge.so (argument marshalling only; every step runs in the
+library's HIP kernels).
+
+A 1 -> 32 (ReLU) -> 1 FP32 network models the cumulative distribution of a
+sorted array; a bounded exponential search from its prediction finds the
+exact cross rank, falling back to the plain binary search of Steps 1-2 when
+the walk would leave the window.  Parameters: 97 device floats
+(W1[0:32], b1[32:64], w2[64:96], b2[96]).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib, _check, _dtype_code, _ptr, _stream_ptr, _require_device, SMError
+
+NPARAM = 97
+HIST_BINS = 65
+HIST_CENTER = 32
+
+_vp, _i64, _i32, _sz, _f32, _u64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t,
+                                    ctypes.c_float, ctypes.c_uint64)
+_lib.sm_mlp_grad_workspace_bytes.restype = _sz
+_lib.sm_mlp_grad_workspace_bytes.argtypes = [_i64]
+_lib.sm_mlp_grad.restype = _i32
+_lib.sm_mlp_grad.argtypes = [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.sm_mlp_adam.restype = _i32
+_lib.sm_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _vp]
+_lib.sm_mlp_init.restype = _i32
+_lib.sm_mlp_init.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp]
+_lib.sm_mlp_predict.restype = _i32
+_lib.sm_mlp_predict.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp]
+_lib.sm_rank_model_workspace_bytes.restype = _sz
+_lib.sm_rank_model_workspace_bytes.argtypes = [_i64, _i32]
+_lib.sm_rank_model_train.restype = _i32
+_lib.sm_rank_model_train.argtypes = [_vp, _i64, _vp, _i64, _i32, _i32, _i64, _i64, _f32, _u64,
+                                     _vp, _vp, _vp, _sz, _vp]
+_lib.stable_merge_rank_search.restype = _i32
+_lib.stable_merge_rank_search.argtypes = [_vp, _i64, _vp, _i64, _i32, _i32, _vp, _i64, _i64, _vp,
+                                          _vp, _vp, _vp]
+_lib.stable_merge_partition_learned.restype = _i32
+_lib.stable_merge_partition_learned.argtypes = [_vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _i64,
+                                                _i64, _i64, _vp, _vp, _vp, _vp, _vp]
+
+
+def _f32_params(p):
+    if p.dtype != torch.float32 or p.numel() != NPARAM or not p.is_cuda or not p.is_contiguous():
+        raise SMError(-1, "params must be a contiguous device float32 tensor of 97 entries")
+
+
+def mlp_grad(params, keys, target, *, stream=None):
+    """(grad[97], loss) of the mean squared normalised-rank error (device tensors)."""
+    _f32_params(params)
+    _require_device(keys, target)
+    S = keys.numel()
+    grad = torch.empty(NPARAM, dtype=torch.float32, device=keys.device)
+    loss = torch.empty(1, dtype=torch.float32, device=keys.device)
+    ws = torch.empty(max(int(_lib.sm_mlp_grad_workspace_bytes(S)), 16), dtype=torch.uint8,
+                     device=keys.device)
+    _check(_lib.sm_mlp_grad(_ptr(params), _ptr(keys), _ptr(target), S, _dtype_code(keys),
+                            _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return grad, loss
+
+
+def mlp_adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, *, stream=None):
+    """One Adam step, in place on params, m and v."""
+    for t in (params, m, v, grad):
+        _f32_params(t)
+    _check(_lib.sm_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr),
+                            float(beta1), float(beta2), float(eps), _stream_ptr(stream)))
+
+
+def mlp_init(sorted_keys, target, *, stream=None):
+    """Interpolating knot initialisation from a sorted sample and its targets."""
+    _require_device(sorted_keys, target)
+    p = torch.empty(NPARAM, dtype=torch.float32, device=sorted_keys.device)
+    _check(_lib.sm_mlp_init(_ptr(sorted_keys), _ptr(target), sorted_keys.numel(),
+                            _dtype_code(sorted_keys), _ptr(p), _stream_ptr(stream)))
+    return p
+
+
+def mlp_predict(params, keys, length, *, stream=None):
+    _f32_params(params)
+    _require_device(keys)
+    out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    _check(_lib.sm_mlp_predict(_ptr(params), _ptr(keys), keys.numel(), _dtype_code(keys),
+                               int(length), _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def train_rank_model(X, Q, is_high, samples=1 << 20, steps=1000, lr=3e-3, seed=0, *,
+                     params=None, workspace=None, stream=None):
+    """Trains a model of sorted X for sorted queries Q.  Returns (params,
+    loss tensor[1]); sqrt(loss) * len(X) is the RMS rank error on the sample."""
+    _require_device(X, Q, params, workspace)
+    code = _dtype_code(X)
+    if params is None:
+        params = torch.empty(NPARAM, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    if workspace is None:
+        need = int(_lib.sm_rank_model_workspace_bytes(samples, code))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
+    _check(_lib.sm_rank_model_train(_ptr(X), X.numel(), _ptr(Q), Q.numel(), code, int(is_high),
+                                    int(samples), int(steps), float(lr), int(seed) & (2 ** 64 - 1),
+                                    _ptr(params), _ptr(loss), _ptr(workspace), workspace.numel(),
+                                    _stream_ptr(stream)))
+    return params, loss
+
+
+def step0_from_loss(loss: float, length: int) -> int:
+    """Initial search step: the largest power of two not above the RMS rank error."""
+    rms = math.sqrt(max(float(loss), 0.0)) * length
+    return 1 << max(0, int(math.floor(math.log2(rms)))) if rms >= 1.0 else 1
+
+
+def rank_search(X, queries, guess, is_high, step0=1, window=256, *, stream=None):
+    """(ranks int64, probes int32, fallback int32) of queries in sorted X."""
+    _require_device(X, queries, guess)
+    q = queries.numel()
+    dev = queries.device
+    ranks = torch.empty(q, dtype=torch.int64, device=dev)
+    probes = torch.empty(q, dtype=torch.int32, device=dev)
+    fb = torch.empty(q, dtype=torch.int32, device=dev)
+    _check(_lib.stable_merge_rank_search(_ptr(X), X.numel(), _ptr(queries), q, _dtype_code(X),
+                                         int(is_high), _ptr(guess), int(step0), int(window),
+                                         _ptr(ranks), _ptr(probes), _ptr(fb), _stream_ptr(stream)))
+    return ranks, probes, fb
+
+
+def partition_learned(keys, n, m, p_a, p_b, model_b, model_a, step0_a=1, step0_b=1, window=256,
+                      *, xbar=None, ybar=None, hist=None, counters=None, stream=None):
+    """Steps 1-2 from learned starting points.  Returns (xbar, ybar, hist,
+    counters) with counters = [searches, fallbacks, probes]; hist and
+    counters are accumulated into when given."""
+    _f32_params(model_b)
+    _f32_params(model_a)
+    _require_device(keys, xbar, ybar, hist, counters)
+    dev = keys.device
+    if xbar is None:
+        xbar = torch.empty(p_a + 1, dtype=torch.int64, device=dev)
+    if ybar is None:
+        ybar = torch.empty(p_b + 1, dtype=torch.int64, device=dev)
+    if hist is None:
+        hist = torch.zeros(HIST_BINS, dtype=torch.uint64, device=dev)
+    if counters is None:
+        counters = torch.zeros(4, dtype=torch.uint64, device=dev)
+    _check(_lib.stable_merge_partition_learned(_ptr(keys), n, m, p_a, p_b, _dtype_code(keys),
+                                               _ptr(model_b), _ptr(model_a), int(step0_a),
+                                               int(step0_b), int(window), _ptr(xbar), _ptr(ybar),
+                                               _ptr(hist), _ptr(counters), _stream_ptr(stream)))
+    return xbar, ybar, hist, counters

@@ -1,0 +1,191 @@
+"""GPU parity of the learned cross-rank path: the network's forward /
+backward / Adam / initialisation against the FP64 oracle (tolerance), the
+bounded search against the oracle's search (bit-exact ranks, probes and
+fallbacks), the learned partition against the oracle's cross ranks
+(bit-exact), and the gain of the trained network over the plain search."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from helpers import dev, flush, host, rand_sorted
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+import paper_1202_6575_amd as sm  # noqa: E402
+from paper_1202_6575_amd import learned  # noqa: E402
+
+DTYPES = [np.int32, np.uint32, np.uint64]
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+def grad_tol(g_ref):
+    return 1e-4 * np.max(np.abs(g_ref)) + 1e-6
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_mlp_grad_matches_oracle(dtype):
+    g = np.random.default_rng(1)
+    for S in (1, 1000, 70_001):
+        keys = rand_sorted(g, S, 1 << 20, dtype)
+        target = f32(g.random(S))
+        params = f32(g.normal(size=mlp.NPARAM) * np.r_[np.full(32, 2.0), np.full(32, 0.5),
+                                                       np.full(33, 0.3)])
+        flush(f"mlp grad dtype={np.dtype(dtype).name} S={S}")
+        grad, loss = learned.mlp_grad(dev(params), dev(keys), dev(target))
+        torch.cuda.synchronize()
+        L_ref, g_ref = mlp.loss_and_grad(params.astype(np.float64), mlp.features(keys),
+                                         target.astype(np.float64))
+        gg = host(grad).astype(np.float64)
+        assert np.all(np.abs(gg - g_ref) <= grad_tol(g_ref)), np.max(np.abs(gg - g_ref))
+        assert abs(float(host(loss)[0]) - L_ref) <= 1e-5 * abs(L_ref) + 1e-9
+
+
+def test_mlp_grad_reproducible():
+    g = np.random.default_rng(2)
+    keys = dev(rand_sorted(g, 300_000, 1 << 30, np.uint32))
+    target = dev(f32(g.random(300_000)))
+    params = dev(f32(g.normal(size=mlp.NPARAM)))
+    a = learned.mlp_grad(params, keys, target)
+    b = learned.mlp_grad(params, keys, target)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_mlp_adam_matches_oracle():
+    g = np.random.default_rng(3)
+    p = f32(g.normal(size=mlp.NPARAM))
+    m = f32(g.normal(size=mlp.NPARAM) * 0.1)
+    v = f32(g.random(mlp.NPARAM) * 0.01)
+    grad = f32(g.normal(size=mlp.NPARAM))
+    for step in (1, 2, 17, 1000):
+        dp, dm, dv = dev(p), dev(m), dev(v)
+        learned.mlp_adam(dp, dm, dv, dev(grad), step, 3e-3)
+        torch.cuda.synchronize()
+        # the oracle takes the same (FP32) hyper-parameters the kernel receives
+        b1, b2, eps, lr = (float(np.float32(x)) for x in (0.9, 0.999, 1e-8, 3e-3))
+        rp, rm, rv = mlp.adam_step(p.astype(np.float64), grad.astype(np.float64),
+                                   m.astype(np.float64), v.astype(np.float64), step, lr,
+                                   b1, b2, eps)
+        # FP32 updates: a few ulps of the largest operand of each update
+        ulp = lambda a: 4 * np.spacing(np.float32(np.max(np.abs(a))))
+        assert np.all(np.abs(host(dm) - rm) <= ulp(m) + ulp(grad) * 0.1)
+        assert np.all(np.abs(host(dv) - rv) <= ulp(v) + ulp(grad * grad) * 1e-3)
+        assert np.all(np.abs(host(dp) - rp) <= ulp(p) + 1e-5 * 3e-3)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_mlp_init_and_predict_match_oracle(dtype):
+    g = np.random.default_rng(4)
+    keys = rand_sorted(g, 40_000, 1 << 16, dtype)
+    target = f32(np.sort(g.random(40_000)))
+    p = learned.mlp_init(dev(keys), dev(target))
+    torch.cuda.synchronize()
+    ref = mlp.init_params(mlp.features(keys), target.astype(np.float64))
+    got = host(p).astype(np.float64)
+    assert np.allclose(got[0:64], ref[0:64], rtol=1e-6, atol=1e-7)
+    assert np.allclose(got[96], ref[96], rtol=1e-6)
+    # output weights are slopes over knot gaps (FP32 features against FP64 ones)
+    assert np.all(np.abs(got[64:96] - ref[64:96]) <= 1e-4 * np.max(np.abs(ref[64:96])) + 1e-6)
+    # predictions of the GPU network against the oracle's own network
+    q = rand_sorted(g, 5000, 1 << 16, dtype)
+    L = 1 << 24
+    rh = host(learned.mlp_predict(p, dev(q), L))
+    rr = mlp.predict_rank(ref, q, L)
+    assert np.max(np.abs(rh - rr)) <= 1e-4 * L + 1
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("is_high", [False, True])
+def test_rank_search_matches_oracle(dtype, is_high):
+    """Guesses = exact rank + seeded errors; every rank, probe count and
+    fallback flag equals the oracle's search."""
+    g = np.random.default_rng(5)
+    X = rand_sorted(g, 100_000, 5000, dtype)
+    Q = rand_sorted(g, 600, 5200, dtype)
+    exact = np.array([oracle.rank_high(x, X) if is_high else oracle.rank_low(x, X) for x in Q])
+    dX, dQ = dev(X), dev(Q)
+    for spread in (0, 3, 100, 5000, 200_000):
+        err = (g.normal(size=len(Q)) * spread).astype(np.int64) if spread else np.zeros(len(Q), np.int64)
+        guess = exact + err
+        for step0 in (1, 4, 64):
+            for window in (0, 16, 1024, 1 << 20):
+                flush(f"search dtype={np.dtype(dtype).name} high={is_high} spread={spread} "
+                      f"step0={step0} W={window}")
+                r, pr, fb = learned.rank_search(dX, dQ, dev(guess), is_high, step0, window)
+                torch.cuda.synchronize()
+                r, pr, fb = host(r), host(pr), host(fb)
+                assert np.array_equal(r, exact)
+                for i in range(0, len(Q), 7):
+                    rr, pp, ff = oracle.gallop(Q[i], X, is_high, int(guess[i]), window, step0)
+                    assert (rr, pp, ff) == (r[i], pr[i], bool(fb[i])), i
+
+
+def train_pair(A, B, samples=1 << 15, steps=400):
+    dA, dB = dev(A), dev(B)
+    pb, lb = learned.train_rank_model(dB, dA, False, samples, steps, seed=11)   # B's CDF, A's queries
+    pa, la = learned.train_rank_model(dA, dB, True, samples, steps, seed=12)    # A's CDF, B's queries
+    torch.cuda.synchronize()
+    return pb, float(host(lb)[0]), pa, float(host(la)[0])
+
+
+def test_learned_partition_exact():
+    """Any window and initial step: the same cross ranks as the oracle."""
+    n, m = 1 << 20, 600_000
+    A = datagen.lognormal_mixture(n, 21)
+    B = datagen.lognormal_mixture(m, 22)
+    pb, lb, pa, la = train_pair(A, B)
+    keys = dev(np.concatenate([A, B]))
+    p_a, p_b = n // 16, (m + 15) // 16
+    xr, yr = oracle.cross_ranks(A, B, p_a, p_b)
+    s0a, s0b = learned.step0_from_loss(lb, m), learned.step0_from_loss(la, n)
+    for (sa, sb, W) in [(1, 1, 0), (1, 1, 64), (s0a, s0b, 1 << 40), (s0a, s0b, 4 * s0a),
+                        (64, 64, 1024)]:
+        flush(f"learned partition step0=({sa},{sb}) W={W}")
+        xb, yb, hist, cnt = learned.partition_learned(keys, n, m, p_a, p_b, pb, pa, sa, sb, W)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(xb), xr) and np.array_equal(host(yb), yr)
+        h, c = host(hist).astype(np.int64), host(cnt).astype(np.int64)
+        assert c[0] == p_a + p_b and h.sum() == c[0]
+        if W == 0:
+            assert c[1] == c[0]                       # every walk is refused: all fall back
+        if W >= 1 << 40:
+            assert c[1] == 0
+    # the ranks drive the merge: output equals the oracle's merge
+    ck, _ = sm.merge_pieces(keys, n, m, p_a, p_b, xb, yb)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ck), oracle.merge(A, B)[0])
+
+
+def test_trained_network_gain():
+    """On the log-normal mixture, the trained network brings the search to
+    fewer probes per rank than the plain binary search (floor(log2 len) + 1
+    reads), and training lowers the rank error of the initial network."""
+    n = m = 1 << 22
+    A = datagen.lognormal_mixture(n, 31)
+    B = datagen.lognormal_mixture(m, 32)
+    dA, dB = dev(A), dev(B)
+    keys = dev(np.concatenate([A, B]))
+    p_a = p_b = n // 16
+    pb0, lb0 = learned.train_rank_model(dB, dA, False, 1 << 16, 0, seed=1)     # init only
+    pb, lb = learned.train_rank_model(dB, dA, False, 1 << 16, 1000, seed=1)
+    pa, la = learned.train_rank_model(dA, dB, True, 1 << 16, 1000, seed=2)
+    torch.cuda.synchronize()
+    lb0, lb, la = float(host(lb0)[0]), float(host(lb)[0]), float(host(la)[0])
+    flush(f"rms before {np.sqrt(lb0) * m:.0f} after {np.sqrt(lb) * m:.0f}")
+    assert lb < lb0
+    s0a, s0b = learned.step0_from_loss(lb, m), learned.step0_from_loss(la, n)
+    xb, yb, hist, cnt = learned.partition_learned(keys, n, m, p_a, p_b, pb, pa, s0a, s0b, 1 << 40)
+    torch.cuda.synchronize()
+    c = host(cnt).astype(np.int64)
+    learned_probes = c[2] / c[0]
+    plain_probes = int(np.floor(np.log2(m))) + 1
+    flush(f"probes per rank: learned {learned_probes:.2f} plain {plain_probes}")
+    assert learned_probes < plain_probes - 3
+    xr, yr = oracle.cross_ranks(A, B, p_a, p_b)
+    assert np.array_equal(host(xb), xr) and np.array_equal(host(yb), yr)

@@ -372,6 +372,32 @@ def test_gallop_exact(is_high):
                     assert probes >= int(np.floor(np.log2(n + 1)))
 
 
+@pytest.mark.parametrize("is_high", [False, True])
+def test_gallop_initial_step(is_high):
+    """Any initial step gives the exact rank; with the step at or above the
+    guess error, the bracket is found by the first move (at most two probes
+    before the bisection of a bracket no wider than the step)."""
+    g = np.random.default_rng(13)
+    for _ in range(400):
+        n = int(g.integers(1, 2000))
+        X = rand_sorted(g, n, int(g.integers(1, 400)), np.uint32)
+        x = rand_sorted(g, 1, 512, np.uint32)[0]
+        r = int(np.sum(X <= x)) if is_high else int(np.sum(X < x))
+        for e in (0, 1, -1, 5, -9, 33, -100, 700):
+            gs = min(max(r + e, 0), n)
+            dist = abs(gs - r)
+            for s0 in (1, 2, 8, 64, 512):
+                for W in (0, 16, 1024, 1 << 20):
+                    got, probes, fb = oracle.gallop(x, X, is_high, r + e, W, step0=s0)
+                    assert got == r
+                    if s0 > W:
+                        # every search moves at least once, and the first move is too far
+                        assert fb
+                    elif s0 >= dist:
+                        # probe g, one step, bisect a bracket of at most s0 elements
+                        assert not fb and probes <= 2 + (s0.bit_length() + 1)
+
+
 # --------------------------------------------------------------------------
 # O7: the predictor network
 # --------------------------------------------------------------------------
@@ -398,6 +424,28 @@ def test_adam_first_step_closed_form():
     p1, m, v = mlp.adam_step(p0, g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(p1, p0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_mlp_init_interpolates_knots():
+    """The initial network passes through every knot (c_k, t_k), is flat at
+    t_0 below the first knot and linear between neighbouring knots."""
+    g = np.random.default_rng(5)
+    phi = np.sort(g.random(5000))
+    target = np.sort(g.random(5000))
+    p = mlp.init_params(phi, target)
+    idx = ((np.arange(32) + 0.5) * 5000 / 32).astype(np.int64)
+    c, t = phi[idx], target[idx]
+    y, _, _ = mlp.forward(p, c)
+    assert np.allclose(y, t, rtol=0, atol=1e-9)
+    below, _, _ = mlp.forward(p, np.array([0.0, c[0] * 0.5]))
+    assert np.allclose(below, t[0], atol=1e-12)
+    mid = (c[:-1] + c[1:]) / 2
+    ym, _, _ = mlp.forward(p, mid)
+    assert np.allclose(ym, (t[:-1] + t[1:]) / 2, atol=1e-9)
+    # tied knots (a run of equal features) give a zero slope, not a division by zero
+    phi2 = np.concatenate([np.zeros(3000), np.linspace(0.5, 1.0, 2000)])
+    p2 = mlp.init_params(phi2, np.linspace(0, 1, 5000))
+    assert np.isfinite(p2).all()
 
 
 def test_mlp_features_order_preserving():
