@@ -260,6 +260,9 @@ def main():
         torch.cuda.empty_cache()
         res["sort"] = bench_sort(args)
         log(f"bench: sort {json.dumps(res['sort'])}")
+        torch.cuda.empty_cache()
+        res["learned"] = bench_learned(args)
+        log(f"bench: learned {json.dumps(res['learned'])}")
     print(json.dumps(res), flush=True)
 
 
@@ -412,6 +415,117 @@ def bench_sort(args):
             "Gelem/s": round(N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3),
             "passes": passes, "output_sorted": sorted_ok,
             "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1)}
+
+
+def _bin_label(k: int) -> str:
+    """Error bin k (predicted - exact): 0, or |e| in [2^(|k|-1), 2^|k|) with its sign."""
+    if k == 0:
+        return "0"
+    lo, hi = 1 << (abs(k) - 1), (1 << abs(k)) - 1
+    sign = "+" if k > 0 else "-"
+    return f"{sign}{lo}" if lo == hi else f"{sign}[{lo},{hi}]"
+
+
+def bench_learned(args):
+    """n = m = 2^28 uint32 keys from a 3-component log-normal mixture, sorted;
+    block starts every 16 elements (2^24 cross ranks per side).  Two rank
+    models (B's CDF for A's block starts, A's CDF for B's) trained on 2^20
+    sampled exact ranks; the learned partition against the plain binary
+    search partition, both followed by the one-lane-per-subproblem merge."""
+    import numpy as np
+    import torch
+    import datagen
+    import datagen.torch_gen as tg
+    import paper_1202_6575_amd as sm
+    from paper_1202_6575_amd import learned
+
+    n = m = 1 << 28
+    log("bench: learned partition, n=m=2^28 log-normal mixture")
+    A = tg.lognormal_mixture(n, seed=datagen.BASE_SEED + 6)
+    B = tg.lognormal_mixture(m, seed=datagen.BASE_SEED + 7)
+    keys = torch.cat([A, B])
+    del A, B
+    torch.cuda.empty_cache()
+    dA, dB = keys[:n], keys[n:]
+    stream = torch.cuda.current_stream()
+    samples, steps = 1 << 20, 1000
+
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    model_b, loss_b = learned.train_rank_model(dB, dA, False, samples, steps, seed=1)
+    model_a, loss_a = learned.train_rank_model(dA, dB, True, samples, steps, seed=2)
+    t1.record(stream)
+    t1.synchronize()
+    train_ms = t0.elapsed_time(t1)
+    lb, la = float(loss_b.item()), float(loss_a.item())
+    s0a, s0b = learned.step0_from_loss(lb, m), learned.step0_from_loss(la, n)
+
+    p_a, p_b = n // 16, m // 16
+    dev = keys.device
+    xp = torch.empty(p_a + 1, dtype=torch.int64, device=dev)
+    yp = torch.empty(p_b + 1, dtype=torch.int64, device=dev)
+    xl, yl = torch.empty_like(xp), torch.empty_like(yp)
+    hist = torch.zeros(learned.HIST_BINS, dtype=torch.uint64, device=dev)
+    cnt = torch.zeros(4, dtype=torch.uint64, device=dev)
+    reps = 5
+
+    def plain():
+        sm.partition(keys, n, m, p_a, p_b, xbar=xp, ybar=yp, stream=stream)
+
+    plain()
+    plain_ms = _events_ms(plain, reps, stream)
+    windows = {}
+    for mult in (4, 64):
+        W = mult * max(s0a, s0b)
+
+        def learned_run():
+            learned.partition_learned(keys, n, m, p_a, p_b, model_b, model_a, s0a, s0b, W,
+                                      xbar=xl, ybar=yl, hist=hist, counters=cnt, stream=stream)
+
+        hist.zero_()
+        cnt.zero_()
+        learned_run()
+        torch.cuda.synchronize()
+        h = hist.cpu().numpy().astype(np.int64)
+        c = cnt.cpu().numpy().astype(np.int64)
+        same = bool(torch.equal(xl, xp) and torch.equal(yl, yp))
+        ms = _events_ms(learned_run, reps, stream)
+        windows[str(W)] = {"ms": round(ms, 4), "ranks_equal_plain": same,
+                           "fallback_rate": round(c[1] / c[0], 5),
+                           "probes_per_rank": round(c[2] / c[0], 3),
+                           "histogram": {_bin_label(i - learned.HIST_CENTER): int(h[i])
+                                         for i in range(len(h)) if h[i]}}
+    best_w = min(windows, key=lambda w: windows[w]["ms"])
+
+    out_p = torch.empty_like(keys)
+    out_l = torch.empty_like(keys)
+    ws = torch.empty(max(sm.pieces_workspace_bytes(n, m, p_a, p_b, torch.uint32), 16),
+                     dtype=torch.uint8, device=dev)
+
+    def merge_with(xb, yb, out):
+        sm.merge_pieces(keys, n, m, p_a, p_b, xb, yb, out_keys=out, workspace=ws, stream=stream)
+
+    merge_with(xp, yp, out_p)
+    merge_with(xl, yl, out_l)
+    torch.cuda.synchronize()
+    outputs_equal = bool(torch.equal(out_p, out_l))
+    fine_ms = _events_ms(lambda: merge_with(xl, yl, out_l), reps, stream)
+    lw = windows[best_w]["ms"]
+    return {"workload": "n=m=2^28 uint32, 3-component log-normal mixture (medians 2^10, 2^20, "
+                        "2^28; sigma 0.5), sorted; block starts every 16 elements",
+            "splitters_per_side": p_a, "train": {"samples": samples, "steps": steps,
+                                                 "ms_both_models": round(train_ms, 2),
+                                                 "rms_rank_error_elements":
+                                                     [round(np.sqrt(lb) * m), round(np.sqrt(la) * n)],
+                                                 "step0": [s0a, s0b]},
+            "plain_partition_ms": round(plain_ms, 4),
+            "plain_probes_per_rank": int(np.floor(np.log2(m))) + 1,
+            "learned_partition": windows, "best_window": int(best_w),
+            "partition_speedup_learned_vs_plain": round(plain_ms / lw, 3),
+            "fine_merge_ms": round(fine_ms, 4), "outputs_bit_equal": outputs_equal,
+            "end_to_end_Gelem/s": {"plain": round((n + m) / ((plain_ms + fine_ms) * 1e-3) / 1e9, 2),
+                                   "learned": round((n + m) / ((lw + fine_ms) * 1e-3) / 1e9, 2)}}
 
 
 if __name__ == "__main__":

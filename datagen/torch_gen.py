@@ -4,6 +4,8 @@ generators in this package; different random streams.  No merge arithmetic
 here: sorting the inputs uses torch.sort."""
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -43,3 +45,21 @@ def sort_input(N: int, key_hi: int, seed: int, device="cuda:0"):
         k.to(torch.uint32)
     pay = torch.arange(N, device=device, dtype=torch.int32).view(torch.uint32)
     return keys, pay
+
+
+def lognormal_mixture(count: int, seed: int, medians_log2=(10, 20, 28), sigma=0.5,
+                      device="cuda:0"):
+    """Sorted uint32 keys: a component is picked uniformly, then
+    key = floor(exp(ln(2^median) + sigma * N(0, 1))) clipped to [0, 2^32 - 1]
+    (the recipe of the numpy generator, drawn on the GPU)."""
+    g = _gen(seed, device)
+    comp = torch.randint(0, len(medians_log2), (count,), generator=g, device=device)
+    mu = torch.tensor([math.log(2.0) * v for v in medians_log2], dtype=torch.float64,
+                      device=device)[comp]
+    del comp
+    x = torch.exp(mu + sigma * torch.randn(count, generator=g, device=device, dtype=torch.float64))
+    del mu
+    x = torch.clamp(torch.floor(x), 0, 2 ** 32 - 1).to(torch.int64)
+    x = torch.sort(x).values
+    # uint32 from the int64 values (two's complement wrap for values >= 2^31)
+    return torch.where(x >= 2 ** 31, x - 2 ** 32, x).to(torch.int32).view(torch.uint32)
