@@ -424,6 +424,33 @@ __device__ __forceinline__ void prefetch(const SegPlan& p, const K* keys, uint64
                            (p.kb_al + p.offB - p.offPB) * 4, p.ncpb, rp);
 }
 
+// The same loads with one buffer resource spanning the whole array, for
+// arrays below 4 GiB: every slot is one load at a 32-bit byte offset, and
+// the registers are not touched again until the commit that consumes them.
+template <int L, int R>
+__device__ __forceinline__ void load_windows_whole(__amdgpu_buffer_rsrc_t r, int64_t wa0, int na,
+                                                   int64_t wb0, int nb, u32x4 (&rk)[R]) {
+    const int t = threadIdx.x;
+    const uint32_t oa = (uint32_t)wa0, ob = (uint32_t)wb0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int q = i * L + t;
+        const uint32_t off = q < na ? oa + q * 16 : (q < na + nb ? ob + (q - na) * 16 : kOffNone);
+        rk[i] = buf_load16(r, off);
+    }
+}
+
+template <typename K, bool PAY, int L, int R>
+__device__ __forceinline__ void prefetch_whole(const SegPlan& p, __amdgpu_buffer_rsrc_t rkeys,
+                                               __amdgpu_buffer_rsrc_t rpay, u32x4 (&rk)[R],
+                                               u32x4 (&rp)[R]) {
+    load_windows_whole<L, R>(rkeys, p.ka_al * (int64_t)sizeof(K), p.nca,
+                             p.kb_al * (int64_t)sizeof(K), p.ncb, rk);
+    if (PAY)
+        load_windows_whole<L, R>(rpay, (p.ka_al + p.offA - p.offPA) * 4, p.ncpa,
+                                 (p.kb_al + p.offB - p.offPB) * 4, p.ncpb, rp);
+}
+
 // A successor slot whose segment ends its source array must hold the key
 // type's maximum.  The lane that wrote the chunk holding the slot overwrites
 // it after its own chunk write, so no other lane races on it.
@@ -434,15 +461,23 @@ __device__ __forceinline__ void fix_successors(const SegPlan& p, K* sKey) {
     if (!p.succB && t == p.qsB % L) sKey[p.wa + p.offB + p.b] = KeyMax<K>::v;
 }
 
+// Wait until at most N vector memory operations of this wave are in flight,
+// without waiting on the other counters (gfx9 s_waitcnt encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8).  Loads complete in
+// issue order, so after wait_vm<N> every load issued before the last N
+// operations has landed.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Registers -> LDS.  The caller has waited for the loads that filled rk / rp.
 template <typename K, bool PAY, int L, int R>
 __device__ __forceinline__ void commit(const SegPlan& p, const u32x4 (&rk)[R],
                                        const u32x4 (&rp)[R], K* sKey, uint32_t* sPay) {
     constexpr int V = Vec<K>::N;
     const int t = threadIdx.x;
-    // one explicit wait for everything in flight (this piece's loads, and
-    // stores issued a whole merge ago): afterwards no register has a load
-    // pending, so the compiler adds no waits further down the iteration
-    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int q = r * L + t;

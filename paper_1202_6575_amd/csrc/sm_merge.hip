@@ -106,6 +106,10 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
         // share one completion counter, so nothing waits on a store until the
         // next commit, a whole merge later.  The write-back reads sOut / sIdx,
         // which this piece's merge rewrites only after its first barrier.
+        // one wait for everything in flight (this piece's loads, and stores
+        // issued a whole merge ago): afterwards no register has a load pending,
+        // so the compiler adds no waits further down the iteration
+        wait_vm<0>();
         commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
         __syncthreads();
         if (more) prefetch<K, PAY, L, R>(nxt, keys, (uint64_t)nkeys, pay, rk, rp);
@@ -114,6 +118,76 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
         prev = cur;
         cur = nxt;
     }
+    write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+}
+
+// The same with two subproblems in flight: while the workgroup merges
+// subproblem w, the loads of w + 1 and w + 2 are in flight in two register
+// sets, so every load has two merges' time to land.  Per step: wait for the
+// oldest set, commit it to LDS, write back w - 1, issue the loads of w + 2
+// into the freed set, merge w.  The write-back precedes the loads, so at the
+// next wait the operations younger than the awaited loads are one
+// write-back and then the other set's loads: waiting until no more than that
+// set's load count is in flight leaves at most that set in flight.
+template <typename K, bool PAY, int L, int R>
+__global__ __launch_bounds__(L) void merge_pipelined_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
+    const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
+    extern __shared__ __align__(16) char smem[];
+    const SmemPtrs<K, PAY, L> sp(smem, cap);
+    if (P_dev) {
+        const int64_t pd = *P_dev;
+        P = pd < P ? (pd > 0 ? pd : 0) : P;
+    }
+    const int64_t G = gridDim.x;
+    const int64_t w0 = (int64_t)blockIdx.x * P / G;
+    const int64_t w1 = ((int64_t)blockIdx.x + 1) * P / G;
+    if (w0 >= w1) return;
+    auto plan_of = [&](int64_t w) {
+        PieceDesc d;
+        d.ka0 = d.kb0 = d.out0 = 0;
+        d.a_f = d.b_f = 0;
+        if (w < w1) {
+            d = desc[w];
+            if (!desc_ok(d, nkeys, nout, cap)) d.a_f = d.b_f = 0;
+        }
+        return make_plan<K, PAY>(d);
+    };
+    u32x4 rkA[R], rpA[R], rkB[R], rpB[R];
+    SegPlan cur = plan_of(w0);
+    SegPlan nxt = plan_of(w0 + 1);
+    SegPlan prev = cur;
+    // Every step issues its loads, also for a subproblem past the range (an
+    // empty one, whose few loads are never used): the awaited set is then
+    // always older than the other set's loads on every path, which is what
+    // lets the wait below (and the compiler's own) leave that set in flight.
+    // the launcher uses this kernel only for arrays below 4 GiB: one buffer
+    // resource spans each whole array
+    const __amdgpu_buffer_rsrc_t rkeys = make_rsrc(keys, (uint64_t)nkeys * sizeof(K));
+    const __amdgpu_buffer_rsrc_t rpay = make_rsrc(PAY ? pay : nullptr, PAY ? (uint64_t)nkeys * 4 : 0);
+    prefetch_whole<K, PAY, L, R>(cur, rkeys, rpay, rkA, rpA);
+    prefetch_whole<K, PAY, L, R>(nxt, rkeys, rpay, rkB, rpB);
+    auto step = [&](u32x4 (&rk)[R], u32x4 (&rp)[R], int64_t w) {
+        const SegPlan nn = plan_of(w + 2);
+        wait_vm<PAY ? 2 * R : R>();
+        commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
+        __syncthreads();
+        if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+        prefetch_whole<K, PAY, L, R>(nn, rkeys, rpay, rk, rp);
+        if (cur.s > 0) merge_lanes<K, PAY, L>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
+        prev = cur;
+        cur = nxt;
+        nxt = nn;
+    };
+    // pairs of steps, then a lone last step: no path through the loop runs a
+    // set's step twice in a row (its loads would then be the youngest)
+    int64_t w = w0;
+    for (; w + 1 < w1; w += 2) {
+        step(rkA, rpA, w);
+        step(rkB, rpB, w + 1);
+    }
+    if (w < w1) step(rkA, rpA, w);
     write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
 }
 
@@ -255,6 +329,26 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
                                     uint32_t* out_pay, int64_t nout, const PieceDesc* desc,
                                     int64_t P, const int64_t* P_dev, uint32_t cap, hipStream_t st) {
     constexpr int L = kMergeThreads;
+    // two register sets in flight where they fit the register budget and one
+    // buffer resource spans each array
+    const bool whole = (uint64_t)nkeys * sizeof(K) < (1ull << 32) - 4096;
+    if (R <= 5 && whole) {
+        auto kern = merge_pipelined_kernel<K, PAY, L, R>;
+        static bool attr2 = false;
+        if (!attr2) {
+            hipError_t e = allow_big_lds(kern);
+            if (e != hipSuccess) return e;
+            attr2 = true;
+        }
+        const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
+        int per_cu = (int)(kMaxLds / lds);
+        if (per_cu > 8) per_cu = 8;
+        if (per_cu < 1) per_cu = 1;
+        int64_t grid = (int64_t)device_cu_count() * per_cu;
+        if (grid > P) grid = P;
+        kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
+        return hipGetLastError();
+    }
     auto kern = merge_persistent_kernel<K, PAY, L, R>;
     static bool attr = false;
     if (!attr) {
