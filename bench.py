@@ -67,7 +67,7 @@ def traffic_from_profile(launch_bytes_alg: float):
     return pmc.get("hbm_bytes_per_launch")
 
 
-MERGE_KERNEL_TAG = "merge_persistent_kernel"
+MERGE_KERNEL_TAG = "merge_pipelined_kernel"
 COPY_KERNEL_TAG = "bitwise_not"
 
 
@@ -99,7 +99,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, log2n: int, out_path: str = PM
     sw = stream_bytes / (w["copy"] * 1024.0)
     fetch_b = f["merge"] * 1024.0 * sf
     write_b = w["merge"] * 1024.0 * sw
-    out = {"kernel": "merge_persistent_kernel<uint32, keys only>",
+    out = {"kernel": "merge_pipelined_kernel<uint32, keys only>",
            "workload": f"n=m=2^{log2n} uint32 uniform, keys only",
            "source_hash": kernel_source_hash(),
            "fetch_kib_per_dispatch": f["merge"], "write_kib_per_dispatch": w["merge"],
@@ -245,7 +245,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile(alg_bytes),
-                     "kernel": "merge_kernel<uint32, keys only>",
+                     "kernel": "merge_pipelined_kernel<uint32, keys only>",
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "copy_reference": {"GB/s": round(alg_bytes / (copy_ms * 1e-3) / 1e9, 1),
