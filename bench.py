@@ -122,7 +122,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare one output with the oracle")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched-merge and merge-sort measurements")
+                    help="skip the batched, sort and learned measurements")
+    ap.add_argument("--extras", default="batched,sort,learned",
+                    help="comma-separated subset of batched, sort, learned")
+    ap.add_argument("--sort-run", type=int, default=512, help="run length of the merge sort")
     ap.add_argument("--batch-log2max", type=int, default=15,
                     help="batched pairs: totals log-uniform in [16, 2^this]")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -255,14 +258,18 @@ def main():
     if not args.no_extras:
         del keys, out, ws, xbar, ybar, A, B
         torch.cuda.empty_cache()
-        res["batched"] = bench_batched(args, gelems)
-        log(f"bench: batched {json.dumps(res['batched'])}")
-        torch.cuda.empty_cache()
-        res["sort"] = bench_sort(args)
-        log(f"bench: sort {json.dumps(res['sort'])}")
-        torch.cuda.empty_cache()
-        res["learned"] = bench_learned(args)
-        log(f"bench: learned {json.dumps(res['learned'])}")
+        extras = set(args.extras.split(","))
+        if "batched" in extras:
+            res["batched"] = bench_batched(args, gelems)
+            log(f"bench: batched {json.dumps(res['batched'])}")
+            torch.cuda.empty_cache()
+        if "sort" in extras:
+            res["sort"] = bench_sort(args)
+            log(f"bench: sort {json.dumps(res['sort'])}")
+            torch.cuda.empty_cache()
+        if "learned" in extras:
+            res["learned"] = bench_learned(args)
+            log(f"bench: learned {json.dumps(res['learned'])}")
     print(json.dumps(res), flush=True)
 
 
@@ -394,12 +401,13 @@ def bench_sort(args):
     log("bench: merge sort of 2^28 (key, index) pairs")
     keys, pay = tg.sort_input(N, 1 << 24, seed=datagen.BASE_SEED + 5)
     ok, op = torch.empty_like(keys), torch.empty_like(pay)
-    ws = torch.empty(sm.sort_workspace_bytes(N, torch.uint32, True), dtype=torch.uint8,
-                     device=keys.device)
+    run_len = args.sort_run
+    ws = torch.empty(sm.sort_workspace_bytes(N, torch.uint32, True, run=run_len),
+                     dtype=torch.uint8, device=keys.device)
     stream = torch.cuda.current_stream()
 
     def run():
-        sm.sort(keys, pay, out_keys=ok, out_payloads=op, workspace=ws, stream=stream)
+        sm.sort(keys, pay, out_keys=ok, out_payloads=op, run=run_len, workspace=ws, stream=stream)
 
     run()
     torch.cuda.synchronize()
@@ -407,11 +415,13 @@ def bench_sort(args):
     sorted_ok = bool((ok64[1:] >= ok64[:-1]).all())
     del ok64
     ms = _events_ms(run, 3, stream)
-    passes = 19
+    passes = 0
+    while (run_len << passes) < N:
+        passes += 1
     # run formation + every pass read and write 8 bytes per element
     alg = N * 8 * 2 * (passes + 1)
-    return {"workload": "N=2^28 uint32 keys uniform in [0, 2^24), uint32 payload = index, "
-                        "runs of 512, 19 merge passes",
+    return {"workload": f"N=2^28 uint32 keys uniform in [0, 2^24), uint32 payload = index, "
+                        f"runs of {run_len}, {passes} merge passes",
             "Gelem/s": round(N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3),
             "passes": passes, "output_sorted": sorted_ok,
             "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1)}

@@ -599,6 +599,44 @@ __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint
     } while (__any(k < len));
 }
 
+// Batcher's odd-even merge network on v[LO..HI] (HI inclusive) at stride R:
+// with both halves sorted, the compare-exchanges leave the whole range
+// sorted.  Fully unrolled: every index is a compile-time constant, so the
+// values stay in registers.
+template <typename K>
+__device__ __forceinline__ void cmp_exchange(K& x, K& y) {
+    const K lo = y < x ? y : x;
+    const K hi = y < x ? x : y;
+    x = lo;
+    y = hi;
+}
+
+template <int I, int END, int STEP, int R>
+struct CmpExchangeRun {
+    template <typename K>
+    static __device__ __forceinline__ void run(K* v) {
+        if constexpr (I < END) {
+            cmp_exchange(v[I], v[I + R]);
+            CmpExchangeRun<I + STEP, END, STEP, R>::run(v);
+        }
+    }
+};
+
+template <int LO, int HI, int R>
+struct OddEvenMerge {
+    template <typename K>
+    static __device__ __forceinline__ void run(K* v) {
+        constexpr int STEP = 2 * R;
+        if constexpr (STEP < HI - LO) {
+            OddEvenMerge<LO, HI, STEP>::run(v);
+            OddEvenMerge<LO + R, HI, STEP>::run(v);
+            CmpExchangeRun<LO + R, HI - R, STEP, R>::template run<K>(v);
+        } else {
+            cmp_exchange(v[LO], v[LO + R]);
+        }
+    }
+};
+
 // Bounds-checked form: each lane stops after its own la + lb outputs.
 template <typename K, bool PAY>
 __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint32_t* sIdx, int ia,

@@ -249,17 +249,27 @@ __global__ __launch_bounds__(kGradThreads) void mlp_grad_kernel(const float* __r
     }
 }
 
-// grad[j] = (sum over blocks, in block order) / S; loss = squared-error sum / S.
-__global__ void mlp_grad_reduce_kernel(const float* __restrict__ partial, int64_t blocks,
-                                       int64_t S, float* __restrict__ grad,
-                                       float* __restrict__ loss) {
-    const int j = threadIdx.x;
-    if (j >= NACC) return;
+// grad[j] = (sum over blocks) / S; loss = squared-error sum / S.  One
+// workgroup per entry j: thread t adds the partial sums of blocks t, t + 256,
+// ... in order, then a fixed butterfly and a fixed LDS sum combine the
+// threads: the same inputs give the same bits.
+__global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(const float* __restrict__ partial,
+                                                              int64_t blocks, int64_t S,
+                                                              float* __restrict__ grad,
+                                                              float* __restrict__ loss) {
+    __shared__ float red[4];
+    const int j = blockIdx.x;
     float s = 0.0f;
-    for (int64_t b = 0; b < blocks; ++b) s += partial[b * NACC + j];
-    const float v = S > 0 ? s / (float)S : 0.0f;
-    if (j < NP) grad[j] = v;
-    else if (loss) *loss = v;
+    for (int64_t b = threadIdx.x; b < blocks; b += 256) s += partial[b * NACC + j];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float tot = (red[0] + red[1]) + (red[2] + red[3]);
+        const float v = S > 0 ? tot / (float)S : 0.0f;
+        if (j < NP) grad[j] = v;
+        else if (loss) *loss = v;
+    }
 }
 
 // Adam (Kingma and Ba, 2015) with bias correction factors c1 = 1 / (1 - b1^t),
@@ -384,9 +394,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 int64_t mlp_grad_blocks(int64_t S) {
-    // about 16 samples per thread, at most 2048 blocks
-    int64_t blocks = (S + kGradThreads * 16 - 1) / (kGradThreads * 16);
-    if (blocks > 2048) blocks = 2048;
+    // about 4 samples per thread, at most 4096 blocks
+    int64_t blocks = (S + kGradThreads * 4 - 1) / (kGradThreads * 4);
+    if (blocks > 4096) blocks = 4096;
     return blocks < 1 ? 1 : blocks;
 }
 
@@ -404,7 +414,7 @@ hipError_t launch_mlp_grad(int dtype, const float* P, const void* keys, const fl
     });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mlp_grad_reduce_kernel<<<1, 128, 0, st>>>(partial, blocks, S, grad, loss);
+    mlp_grad_reduce_kernel<<<NACC, 256, 0, st>>>(partial, blocks, S, grad, loss);
     return hipGetLastError();
 }
 

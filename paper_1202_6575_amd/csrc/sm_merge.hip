@@ -252,6 +252,45 @@ __global__ __launch_bounds__(256) void fine_merge_kernel(const K* __restrict__ k
     }
 }
 
+// Keys-only form for parts of at most NB elements each: the lane loads its
+// A part and its B part into registers (positions past a part hold the key
+// type's maximum), merges the 2 NB keys with a merging network, and stores
+// the first la + lb.  Without payloads equal keys are indistinguishable, so
+// the network's order among ties does not matter.  All loads of a lane are
+// independent, so they are in flight together.
+template <typename K, int NB>
+__global__ __launch_bounds__(256) void fine_merge_net_kernel(const K* __restrict__ keys, int64_t n,
+                                                             int64_t m, int64_t p_a, int64_t p_b,
+                                                             const int64_t* __restrict__ xbar,
+                                                             const int64_t* __restrict__ ybar,
+                                                             K* __restrict__ out) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= p_a + p_b) return;
+    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
+    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
+                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
+    const int64_t la = pc.a_hi - pc.a_lo, lb = pc.b_hi - pc.b_lo;
+    if (!(0 <= pc.a_lo && la >= 0 && pc.a_hi <= n && 0 <= pc.b_lo && lb >= 0 && pc.b_hi <= m &&
+          la <= NB && lb <= NB))
+        return;  // cannot happen for cross ranks of sorted inputs; never write outside C
+    const int64_t last = n + m - 1;
+    K v[2 * NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int64_t ia = pc.a_lo + i < last ? pc.a_lo + i : last;
+        const int64_t ib = n + pc.b_lo + i < last ? n + pc.b_lo + i : last;
+        const K ka = keys[ia], kb = keys[ib];
+        v[i] = i < la ? ka : KeyMax<K>::v;
+        v[NB + i] = i < lb ? kb : KeyMax<K>::v;
+    }
+    OddEvenMerge<0, 2 * NB - 1, 1>::template run<K>(v);
+    K* o = out + pc.a_lo + pc.b_lo;
+    const int len = (int)(la + lb);
+#pragma unroll
+    for (int k = 0; k < 2 * NB; ++k)
+        if (k < len) o[k] = v[k];
+}
+
 template <typename K>
 __global__ __launch_bounds__(256) void validate_kernel(const K* __restrict__ keys, int64_t n,
                                                        int64_t m, int* flag) {
@@ -434,9 +473,17 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
     const int64_t P = p_a + p_b;
     if (P <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((P + 255) / 256);
+    // parts are bounded by the block lengths
+    const int64_t la_max = p_a > 0 ? (n + p_a - 1) / p_a : 0;
+    const int64_t lb_max = p_b > 0 ? (m + p_b - 1) / p_b : 0;
+    const bool net = !pay && n + m > 0 && la_max <= 16 && lb_max <= 16;
     with_dtype(dtype, [&](auto z) {
         using K = decltype(z);
-        if (pay)
+        if (net)
+            fine_merge_net_kernel<K, 16><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), n, m, p_a,
+                                                               p_b, xbar, ybar,
+                                                               static_cast<K*>(out_keys));
+        else if (pay)
             fine_merge_kernel<K, true><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), pay, n, m,
                                                              p_a, p_b, xbar, ybar,
                                                              static_cast<K*>(out_keys), out_pay);

@@ -161,6 +161,20 @@ def test_special_cases(dtype):
         check(A, B, True, tile=1)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_blocks_keys_only(dtype):
+    """Blocks of at most 16 elements without payloads: the one-lane-per-
+    subproblem merge that loads each part into registers."""
+    g = np.random.default_rng(8)
+    for n, m, alpha in [(5000, 3001, 7), (1, 999, 3), (999, 1, 3), (40_000, 40_000, 1 << 30),
+                        (17, 0, 5), (0, 33, 5)]:
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        for kw in (dict(tile=1), dict(tile=7), dict(tile=16),
+                   dict(p_a=max(1, n // 16), p_b=max(1, m // 16))):
+            flush(f"small blocks dtype={np.dtype(dtype).name} n={n} m={m} {kw}")
+            check(A, B, False, **kw)
+
+
 def test_validate_detects_unsorted():
     A = np.array([1, 2, 3, 2], dtype=np.uint32)
     B = np.array([1, 5], dtype=np.uint32)
