@@ -154,7 +154,7 @@ def main():
     dev = torch.device("cuda:0")
     keys = torch.from_numpy(np.concatenate([A, B])).to(dev)
     out = torch.empty(n + m, dtype=torch.uint32, device=dev)
-    tile = args.tile or 2048
+    tile = args.tile or 2368      # the library's default block length for 32-bit keys
     p_a = (n + tile - 1) // tile
     p_b = (m + tile - 1) // tile
     xbar = torch.empty(p_a + 1, dtype=torch.int64, device=dev)

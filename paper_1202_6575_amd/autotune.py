@@ -21,7 +21,7 @@ import statistics
 
 import torch
 
-TILES = (512, 1024, 1536, 2048, 3072, 4096)
+TILES = (512, 1024, 1152, 1536, 2048, 2368, 3072, 4096)
 
 
 def cache_path() -> str:

@@ -52,8 +52,13 @@ bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Block length in elements when none is given: a subproblem then holds up to
-// twice this, and one merge workgroup stages it in LDS.
-int32_t default_tile(int dtype, bool pay) { return dtype == SM_UINT64 && pay ? 1024 : 2048; }
+// twice this, and one merge workgroup stages it in LDS.  Each is the largest
+// length (measured on MI355X) at which four merge workgroups still share a
+// compute unit's 160 KiB of LDS.
+int32_t default_tile(int dtype, bool pay) {
+    if (dtype == SM_UINT64) return pay ? 1024 : 1152;
+    return pay ? 1152 : 2368;
+}
 
 int32_t pick_tile(int dtype, bool pay, const sm_options* opt) {
     return opt && opt->tile != 0 ? opt->tile : default_tile(dtype, pay);
