@@ -394,8 +394,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 int64_t mlp_grad_blocks(int64_t S) {
-    // about 4 samples per thread, at most 4096 blocks
-    int64_t blocks = (S + kGradThreads * 4 - 1) / (kGradThreads * 4);
+    // about 8 samples per thread (the per-block reduction of 98 sums costs
+    // about as much as a few samples), at most 4096 blocks
+    int64_t blocks = (S + kGradThreads * 8 - 1) / (kGradThreads * 8);
     if (blocks > 4096) blocks = 4096;
     return blocks < 1 ? 1 : blocks;
 }
