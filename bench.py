@@ -123,8 +123,8 @@ def main():
     ap.add_argument("--check", action="store_true", help="compare one output with the oracle")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, sort and learned measurements")
-    ap.add_argument("--extras", default="batched,sort,learned",
-                    help="comma-separated subset of batched, sort, learned")
+    ap.add_argument("--extras", default="batched,batched_literal,sort,learned",
+                    help="comma-separated subset of batched, batched_literal, sort, learned")
     ap.add_argument("--sort-run", type=int, default=512, help="run length of the merge sort")
     ap.add_argument("--batch-log2max", type=int, default=15,
                     help="batched pairs: totals log-uniform in [16, 2^this]")
@@ -260,8 +260,13 @@ def main():
         torch.cuda.empty_cache()
         extras = set(args.extras.split(","))
         if "batched" in extras:
-            res["batched"] = bench_batched(args, gelems)
+            res["batched"] = bench_batched(args, gelems, args.batch_log2max)
             log(f"bench: batched {json.dumps(res['batched'])}")
+            torch.cuda.empty_cache()
+        if "batched_literal" in extras:
+            # pair totals log-uniform up to 2^20: about 6.2e9 elements
+            res["batched_literal"] = bench_batched(args, gelems, 20)
+            log(f"bench: batched_literal {json.dumps(res['batched_literal'])}")
             torch.cuda.empty_cache()
         if "sort" in extras:
             res["sort"] = bench_sort(args)
@@ -286,11 +291,12 @@ def _events_ms(fn, steps, stream):
     return a.elapsed_time(b) / steps
 
 
-def bench_batched(args, plain_gelems):
-    """65,536 independent pairs, totals L_k log-uniform in [16, 2^15] (about
-    2^28 int32 keys in [0, 2^20)), keys only: the batched merge captured in
-    one graph, the tile chosen by the autotuner, against one stable_merge
-    call per pair on a sample of pairs."""
+def bench_batched(args, plain_gelems, log2max):
+    """65,536 independent pairs, totals L_k log-uniform in [16, 2^log2max]
+    (2^15: about 2^28 int32 keys; 2^20, the literal recipe: about 6.2e9),
+    keys uniform in [0, 2^20), keys only: the batched merge captured in one
+    graph, the tile chosen by the autotuner, against one stable_merge call
+    per pair on a sample of pairs."""
     import numpy as np
     import torch
     import datagen
@@ -299,8 +305,8 @@ def bench_batched(args, plain_gelems):
     from paper_1202_6575_amd import autotune
 
     count = 65536
-    log(f"bench: batched merge, {count} pairs, totals in [16, 2^{args.batch_log2max}]")
-    n_k, m_k = datagen.batch_lengths(count, 4, args.batch_log2max, seed=datagen.BASE_SEED + 4)
+    log(f"bench: batched merge, {count} pairs, totals in [16, 2^{log2max}]")
+    n_k, m_k = datagen.batch_lengths(count, 4, log2max, seed=datagen.BASE_SEED + 4)
     keys, offsets, n_a = tg.batched_pairs(n_k, m_k, 0, 1 << 20, seed=datagen.BASE_SEED + 4)
     total = keys.numel()
     out = torch.empty_like(keys)
@@ -374,7 +380,7 @@ def bench_batched(args, plain_gelems):
     per_pair()
     pp_ms = _events_ms(per_pair, 2, stream)
     pp_gel = float(lens.sum()) / (pp_ms * 1e-3) / 1e9
-    return {"workload": f"{count} pairs, L_k = floor(2^U), U ~ U[4, {args.batch_log2max}], "
+    return {"workload": f"{count} pairs, L_k = floor(2^U), U ~ U[4, {log2max}], "
                         f"m_k = floor(f L_k), int32 keys uniform in [0, 2^20), keys only",
             "total_elements": total, "Gelem/s": round(gel, 2), "ms": round(graph_ms, 4),
             "eager_ms": round(eager_ms, 4), "graph_launches_per_step": 1,

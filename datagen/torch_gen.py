@@ -16,25 +16,43 @@ def _gen(seed: int, device) -> torch.Generator:
     return g
 
 
-def batched_pairs(n_k, m_k, lo: int, hi: int, seed: int, device="cuda:0"):
-    """int32 keys uniform in [lo, hi), laid out A_0 || B_0 || A_1 || B_1 ...
-    with every A_k and B_k sorted.  Returns device tensors (keys, offsets[count+1],
-    n_a[count]) (int32, int64, int64)."""
-    n_k = torch.as_tensor(np.asarray(n_k, np.int64), device=device)
-    m_k = torch.as_tensor(np.asarray(m_k, np.int64), device=device)
-    tot = n_k + m_k
-    offsets = torch.zeros(len(tot) + 1, dtype=torch.int64, device=device)
-    torch.cumsum(tot, 0, out=offsets[1:])
-    total = int(offsets[-1])
+def _sorted_runs(run_len, lo: int, hi: int, g, device):
+    """Concatenated runs of the given lengths, each sorted, int32 keys
+    uniform in [lo, hi)."""
     span = hi - lo
     bits = max(1, int(span - 1).bit_length())
-    keys = torch.randint(0, span, (total,), generator=_gen(seed, device), device=device,
-                         dtype=torch.int64)
-    run_len = torch.stack([n_k, m_k], 1).reshape(-1)
+    total = int(run_len.sum())
+    keys = torch.randint(0, span, (total,), generator=g, device=device, dtype=torch.int64)
     run_id = torch.repeat_interleave(torch.arange(len(run_len), device=device), run_len)
     comp = torch.sort((run_id << bits) | keys).values
-    keys = ((comp & ((1 << bits) - 1)) + lo).to(torch.int32)
-    return keys, offsets, n_k.clone()
+    return ((comp & ((1 << bits) - 1)) + lo).to(torch.int32)
+
+
+def batched_pairs(n_k, m_k, lo: int, hi: int, seed: int, device="cuda:0",
+                  chunk: int = 1 << 28):
+    """int32 keys uniform in [lo, hi), laid out A_0 || B_0 || A_1 || B_1 ...
+    with every A_k and B_k sorted.  Returns device tensors (keys, offsets[count+1],
+    n_a[count]) (int32, int64, int64).  Pairs are generated in groups of about
+    `chunk` elements, so totals far above 2^31 fit."""
+    n_np = np.asarray(n_k, np.int64)
+    m_np = np.asarray(m_k, np.int64)
+    tot_np = n_np + m_np
+    off_np = np.zeros(len(tot_np) + 1, dtype=np.int64)
+    np.cumsum(tot_np, out=off_np[1:])
+    total = int(off_np[-1])
+    keys = torch.empty(total, dtype=torch.int32, device=device)
+    g = _gen(seed, device)
+    k0 = 0
+    while k0 < len(tot_np):
+        # pairs [k0, k1) with about `chunk` elements (at least one pair)
+        k1 = int(np.searchsorted(off_np, off_np[k0] + chunk, side="right")) - 1
+        k1 = min(max(k1, k0 + 1), len(tot_np))
+        rl = np.stack([n_np[k0:k1], m_np[k0:k1]], 1).reshape(-1)
+        keys[off_np[k0]:off_np[k1]] = _sorted_runs(torch.as_tensor(rl, device=device), lo, hi,
+                                                   g, device)
+        k0 = k1
+    offsets = torch.as_tensor(off_np, device=device)
+    return keys, offsets, torch.as_tensor(n_np, device=device)
 
 
 def sort_input(N: int, key_hi: int, seed: int, device="cuda:0"):

@@ -153,3 +153,26 @@ def test_config4a_variant_sampled():
     comp_out = torch.from_numpy(pair_id << 21 | got.astype(np.int64)).to("cuda:0")
     assert bool((comp_out[1:] >= comp_out[:-1]).all())
     assert torch.equal(torch.sort(comp_in).values, comp_out)
+
+
+@pytest.mark.slow
+def test_config4a_literal_sampled():
+    """The literal batch recipe: 65,536 pairs with totals log-uniform in
+    [16, 2^20] (about 6.2e9 int32 keys in [0, 2^20), generated on the GPU),
+    merged in the default launch configuration; 256 sampled pairs against
+    the oracle."""
+    import datagen.torch_gen as tg
+    count = 65536
+    n_k, m_k = datagen.batch_lengths(count, 4, 20, seed=datagen.BASE_SEED + 4)
+    flush("config4a literal generate")
+    keys, offsets, n_a = tg.batched_pairs(n_k, m_k, 0, 1 << 20, seed=datagen.BASE_SEED + 4)
+    flush(f"config4a literal gpu total={keys.numel()}")
+    ck, _ = sm.merge_batched(keys, offsets, n_a)
+    torch.cuda.synchronize()
+    off, na = host(offsets), host(n_a)
+    g = np.random.default_rng(2)
+    for k in g.choice(count, 256, replace=False):
+        lo, hi = int(off[k]), int(off[k + 1])
+        inp = host(keys[lo:hi])
+        rk, _ = oracle.merge(inp[:na[k]], inp[na[k]:])
+        assert np.array_equal(host(ck[lo:hi]), rk), f"pair {k}"
