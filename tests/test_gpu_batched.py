@@ -127,17 +127,17 @@ def test_batched_invalid_pair_skipped():
 
 
 @pytest.mark.slow
-def test_config4a_variant_sampled():
+def test_batched_65536_pairs_to_2e15_sampled():
     """65,536 pairs with log-uniform totals in [16, 2^15] (about 2^28 int32
     keys in [0, 2^20)), default launch configuration: 1024 sampled pairs
     against the oracle, and every pair's output a sorted permutation of its
     input (checked on the GPU with torch)."""
     count = 65536
     n_k, m_k = datagen.batch_lengths(count, 4, 15, seed=datagen.BASE_SEED + 4)
-    flush("config4a variant generate")
+    flush("65,536 pairs up to 2^15 generate")
     keys, offsets, n_a = datagen.batched_pairs(n_k, m_k, 0, 1 << 20, np.int32,
                                                seed=datagen.BASE_SEED + 4)
-    flush(f"config4a variant gpu total={len(keys)}")
+    flush(f"65,536 pairs up to 2^15 gpu total={len(keys)}")
     dk = dev(keys)
     ck, _ = sm.merge_batched(dk, dev(offsets), dev(n_a))
     torch.cuda.synchronize()
@@ -156,7 +156,7 @@ def test_config4a_variant_sampled():
 
 
 @pytest.mark.slow
-def test_config4a_literal_sampled():
+def test_batched_65536_pairs_to_2e20_sampled():
     """The literal batch recipe: 65,536 pairs with totals log-uniform in
     [16, 2^20] (about 6.2e9 int32 keys in [0, 2^20), generated on the GPU),
     merged in the default launch configuration; 256 sampled pairs against
@@ -164,9 +164,9 @@ def test_config4a_literal_sampled():
     import datagen.torch_gen as tg
     count = 65536
     n_k, m_k = datagen.batch_lengths(count, 4, 20, seed=datagen.BASE_SEED + 4)
-    flush("config4a literal generate")
+    flush("65,536 pairs up to 2^20 generate")
     keys, offsets, n_a = tg.batched_pairs(n_k, m_k, 0, 1 << 20, seed=datagen.BASE_SEED + 4)
-    flush(f"config4a literal gpu total={keys.numel()}")
+    flush(f"65,536 pairs up to 2^20 gpu total={keys.numel()}")
     ck, _ = sm.merge_batched(keys, offsets, n_a)
     torch.cuda.synchronize()
     off, na = host(offsets), host(n_a)

@@ -69,18 +69,18 @@ def test_partition_matches_oracle(dtype):
         assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
 
 
-def test_config1_partition_p256():
+def test_int32_1m_600k_partition_p256():
     """The config-1 arrays (int32 uniform in [0, 65536), n = 1e6, m = 6e5), p = 256."""
     A, B = datagen.uniform_pair(1_000_000, 600_000, 0, 65536, np.int32, seed=datagen.BASE_SEED)
-    flush("config1 partition p=256")
+    flush("int32 1,000,000 + 600,000 partition p=256")
     xb, yb = sm.partition(dev(np.concatenate([A, B])), len(A), len(B), 256)
     rx, ry = oracle.cross_ranks(A, B, 256)
     assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
 
 
-def test_config1_merge_p256():
+def test_int32_1m_600k_merge_p256():
     A, B = datagen.uniform_pair(1_000_000, 600_000, 0, 65536, np.int32, seed=datagen.BASE_SEED)
-    flush("config1 merge p=256 and auto")
+    flush("int32 1,000,000 + 600,000 merge p=256 and auto")
     check(A, B, p_a=256, p_b=256)
     check(A, B)
 
@@ -200,37 +200,37 @@ def test_unaligned_view():
 
 
 @pytest.mark.slow
-def test_config2_full_size():
+def test_uniform_u32_2x2e28_full():
     """n = m = 2^28 uint32 uniform over the full range, keys only: the whole
     output against the oracle, in the default launch configuration."""
     n = m = 1 << 28
-    flush("config2 generate")
+    flush("uniform uint32 2^28 + 2^28 generate")
     A, B = datagen.uniform_pair(n, m, 0, 2 ** 32, np.uint32, seed=datagen.BASE_SEED + 1)
     keys = dev(np.concatenate([A, B]))
-    flush("config2 gpu merge")
+    flush("uniform uint32 2^28 + 2^28 gpu merge")
     ck, _ = sm.merge(keys, n, m)
     torch.cuda.synchronize()
     got = host(ck)
     del keys, ck
-    flush("config2 oracle merge")
+    flush("uniform uint32 2^28 + 2^28 oracle merge")
     ref, _ = oracle.merge(A, B)
     assert np.array_equal(got, ref)
 
 
 @pytest.mark.slow
-def test_config3_full_size():
+def test_zipf_u64_2e27_2e23_full():
     """n = 2^27, m = 2^23 uint64 Zipf(1.1) keys, payload = concatenated index."""
     n, m = 1 << 27, 1 << 23
-    flush("config3 generate")
+    flush("zipf uint64 2^27 + 2^23 generate")
     A, B = datagen.zipf_pair(n, m, 1.1, 10 ** 6, seed=datagen.BASE_SEED + 2)
     pa, pb = datagen.index_payloads(n, m)
     keys = dev(np.concatenate([A, B]))
     pay = dev(np.concatenate([pa, pb]))
-    flush("config3 gpu merge")
+    flush("zipf uint64 2^27 + 2^23 gpu merge")
     ck, cp = sm.merge(keys, n, m, pay)
     torch.cuda.synchronize()
     gk, gp = host(ck), host(cp)
     del keys, pay, ck, cp
-    flush("config3 oracle merge")
+    flush("zipf uint64 2^27 + 2^23 oracle merge")
     rk, rp = oracle.merge(A, B, pa, pb)
     assert np.array_equal(gk, rk) and np.array_equal(gp, rp)

@@ -90,16 +90,16 @@ def test_sort_alias_rejected():
 
 
 @pytest.mark.slow
-def test_config4b_full_size():
+def test_sort_u32_2e28_full():
     """N = 2^28 uint32 keys uniform in [0, 2^24), payload = index, runs of
     512 and 19 merge passes.  With distinct payloads in input order the
     stable sort is the unique order by (key, payload): the output must be a
     permutation of the input pairs that is strictly increasing in that order."""
     N = 1 << 28
-    flush("config4b generate")
+    flush("sort 2^28 generate")
     keys, pay = datagen.sort_input(N, 1 << 24, seed=datagen.BASE_SEED + 5)
     dk, dp = dev(keys), dev(pay)
-    flush("config4b gpu sort")
+    flush("sort 2^28 gpu sort")
     ck, cp = sm.sort(dk, dp)
     torch.cuda.synchronize()
     comp = ck.to(torch.int64) << 32 | cp.to(torch.int64)
@@ -109,7 +109,7 @@ def test_config4b_full_size():
                  torch.arange(N, device=cp.device)).all())
     assert torch.equal(dk.to(torch.int64)[cp.to(torch.int64)], ck.to(torch.int64))
     # sampled windows against the oracle's merge sort of the same input
-    flush("config4b oracle check on a prefix")
+    flush("sort 2^28 oracle check on a prefix")
     M = 1 << 20
     rk, rp = oracle.sort(keys[:M], pay[:M], 512)
     sub, _ = sm.sort(dev(keys[:M]), dev(pay[:M]))

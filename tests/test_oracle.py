@@ -468,7 +468,7 @@ def test_error_bins():
 # A config-1 shaped case: heavy duplicates, p = 256
 # --------------------------------------------------------------------------
 
-def test_config1_shape_small():
+def test_int32_heavy_ties_shape_small():
     g = np.random.default_rng(17)
     A = np.sort(g.integers(0, 65536, size=200_000).astype(np.int32))
     B = np.sort(g.integers(0, 65536, size=120_000).astype(np.int32))
