@@ -745,10 +745,18 @@ __device__ __forceinline__ void write_out(const E* sArr, int off, int s, E* base
         *reinterpret_cast<u32x4*>(base_out + q * V) = *reinterpret_cast<const u32x4*>(sArr + q * V);
     };
     if (RW > 0) {
+        // all LDS reads first (a chunk past the end re-reads chunk q0 and is
+        // not stored), so one wait covers them, then the stores
+        u32x4 v[RW > 0 ? RW : 1];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int q = q0 + r * L + t;
-            if (q < q1) chunk(q);
+            v[r] = *reinterpret_cast<const u32x4*>(sArr + (q < q1 ? q : q0) * V);
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int q = q0 + r * L + t;
+            if (q < q1) *reinterpret_cast<u32x4*>(base_out + q * V) = v[r];
         }
     } else {
         for (int q = q0 + t; q < q1; q += L) chunk(q);

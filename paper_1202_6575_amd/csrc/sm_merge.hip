@@ -130,7 +130,7 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
 // write-back and then the other set's loads: waiting until no more than that
 // set's load count is in flight leaves at most that set in flight.
 template <typename K, bool PAY, int L, int R>
-__global__ __launch_bounds__(L) void merge_pipelined_kernel(
+__device__ __forceinline__ void merge_pipelined(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
     const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
@@ -189,6 +189,25 @@ __global__ __launch_bounds__(L) void merge_pipelined_kernel(
     }
     if (w < w1) step(rkA, rpA, w);
     write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+}
+
+// Four waves per SIMD need at most 128 registers per lane: four workgroups
+// per compute unit then fit both registers and LDS.  64-bit keys with
+// payloads need more (the wide form, three workgroups).
+template <typename K, bool PAY, int L, int R>
+__global__ __launch_bounds__(L) __attribute__((amdgpu_waves_per_eu(4))) void merge_pipelined_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
+    const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
+    merge_pipelined<K, PAY, L, R>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
+}
+
+template <typename K, bool PAY, int L, int R>
+__global__ __launch_bounds__(L) void merge_pipelined_wide_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
+    const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
+    merge_pipelined<K, PAY, L, R>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
 }
 
 // One workgroup per subproblem, staged straight into LDS; for subproblems
@@ -371,22 +390,30 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
     // two register sets in flight where they fit the register budget and one
     // buffer resource spans each array
     const bool whole = (uint64_t)nkeys * sizeof(K) < (1ull << 32) - 4096;
-    if (R <= 5 && whole) {
-        auto kern = merge_pipelined_kernel<K, PAY, L, R>;
-        static bool attr2 = false;
-        if (!attr2) {
-            hipError_t e = allow_big_lds(kern);
-            if (e != hipSuccess) return e;
-            attr2 = true;
+    if constexpr (R <= 5) {
+        if (whole) {
+            auto go = [&](auto kern, bool& attr2) -> hipError_t {
+                if (!attr2) {
+                    hipError_t e = allow_big_lds(kern);
+                    if (e != hipSuccess) return e;
+                    attr2 = true;
+                }
+                const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
+                int per_cu = (int)(kMaxLds / lds);
+                if (per_cu > 8) per_cu = 8;
+                if (per_cu < 1) per_cu = 1;
+                int64_t grid = (int64_t)device_cu_count() * per_cu;
+                if (grid > P) grid = P;
+                kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P,
+                                                     P_dev, cap);
+                return hipGetLastError();
+            };
+            static bool attr2 = false;
+            if constexpr (sizeof(K) == 8 && PAY)
+                return go(merge_pipelined_wide_kernel<K, PAY, L, R>, attr2);
+            else
+                return go(merge_pipelined_kernel<K, PAY, L, R>, attr2);
         }
-        const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
-        int per_cu = (int)(kMaxLds / lds);
-        if (per_cu > 8) per_cu = 8;
-        if (per_cu < 1) per_cu = 1;
-        int64_t grid = (int64_t)device_cu_count() * per_cu;
-        if (grid > P) grid = P;
-        kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
-        return hipGetLastError();
     }
     auto kern = merge_persistent_kernel<K, PAY, L, R>;
     static bool attr = false;
