@@ -21,13 +21,6 @@ hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m,
 
 struct PieceDesc;
 
-// Steps 3-4 plus the merges: the case-selection kernel writes p_a + p_b
-// descriptors into desc, then the merge kernel merges them.
-hipError_t launch_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n, int64_t m,
-                        int64_t p_a, int64_t p_b, const int64_t* xbar, const int64_t* ybar,
-                        PieceDesc* desc, void* out_keys, uint32_t* out_pay, uint32_t cap,
-                        hipStream_t st);
-
 // Steps 3-4 case selection alone.
 hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                         const int64_t* ybar, PieceDesc* desc, hipStream_t st);

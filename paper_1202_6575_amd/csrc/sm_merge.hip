@@ -483,16 +483,6 @@ hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, i
     return e;
 }
 
-hipError_t launch_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n, int64_t m,
-                        int64_t p_a, int64_t p_b, const int64_t* xbar, const int64_t* ybar,
-                        PieceDesc* desc, void* out_keys, uint32_t* out_pay, uint32_t cap,
-                        hipStream_t st) {
-    hipError_t e = launch_cases(n, m, p_a, p_b, xbar, ybar, desc, st);
-    if (e != hipSuccess) return e;
-    return launch_merge_desc(dtype, keys, pay, n + m, out_keys, out_pay, n + m, desc, p_a + p_b,
-                             nullptr, cap, st);
-}
-
 hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, int64_t n,
                             int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                             const int64_t* ybar, void* out_keys, uint32_t* out_pay,

@@ -234,3 +234,43 @@ def test_zipf_u64_2e27_2e23_full():
     flush("zipf uint64 2^27 + 2^23 oracle merge")
     rk, rp = oracle.merge(A, B, pa, pb)
     assert np.array_equal(gk, rk) and np.array_equal(gp, rp)
+
+
+@pytest.mark.slow
+def test_beyond_32bit_indices():
+    """n = m = 2^31 uint32 keys (2^32 elements, 16 GiB per array): indices
+    and byte offsets past 32 bits, and windows far apart in one buffer.
+    Keys are built sorted on the GPU as prefix sums of 0/1 steps (heavy
+    ties).  Checks: the output is non-decreasing, and for sampled elements
+    of A and of B the oracle's cross rank gives the output slot holding
+    exactly that key (a stable merge puts A[i] at i + rank_low(A[i], B) and
+    B[j] at j + rank_high(B[j], A))."""
+    n = m = 1 << 31
+    dev_ = torch.device("cuda:0")
+    gen = torch.Generator(device=dev_)
+    gen.manual_seed(datagen.BASE_SEED + 9)
+    flush("2^31 + 2^31 generate")
+    keys = torch.empty(n + m, dtype=torch.int32, device=dev_)
+    for lo in (0, n):
+        steps = torch.randint(0, 2, (n,), generator=gen, device=dev_, dtype=torch.int32)
+        keys[lo:lo + n] = torch.cumsum(steps, 0, dtype=torch.int32)
+        del steps
+    keys = keys.view(torch.uint32)
+    flush("2^31 + 2^31 gpu merge")
+    out, _ = sm.merge(keys, n, m)
+    torch.cuda.synchronize()
+    o32 = out.view(torch.int32)
+    for lo in range(0, n + m, 1 << 30):
+        hi = min(lo + (1 << 30) + 1, n + m)
+        assert bool((o32[lo + 1:hi] >= o32[lo:hi - 1]).all()), f"not sorted near {lo}"
+    flush("2^31 + 2^31 sampled ranks")
+    A = host(keys[:n])
+    B = host(keys[n:])
+    g = np.random.default_rng(3)
+    ia = g.integers(0, n, 3000)
+    jb = g.integers(0, m, 3000)
+    pos = np.concatenate([ia + np.array([oracle.rank_low(A[i], B) for i in ia]),
+                          jb + np.array([oracle.rank_high(B[j], A) for j in jb])])
+    want = np.concatenate([A[ia], B[jb]])
+    got = host(o32[torch.as_tensor(pos, device=dev_)]).view(np.uint32)
+    assert np.array_equal(got, want)
