@@ -72,8 +72,8 @@ typedef enum {
  *  validate   nonzero: first check that A and B are non-decreasing (one extra
  *             read of the keys and a synchronisation with the host).
  *  run        stable_merge_sort only: length of the runs sorted inside one
- *             workgroup before the merge passes; 256, 512, 1024 or 2048
- *             (0 = 512).
+ *             workgroup before the merge passes; 256, 512, 1024, 2048, or
+ *             4096 for 32-bit keys (0 = 512).
  *  reserved   must be zero.
  */
 typedef struct {

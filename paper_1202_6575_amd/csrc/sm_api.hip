@@ -356,7 +356,8 @@ int sort_plan(int64_t N, int dtype, bool pay, const sm_options* opt, int* run, i
     if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
     if (N < 0 || N >= (1ll << 31)) return fail(SM_ERR_ARG, "N must be in [0, 2^31)");
     *run = opt && opt->run != 0 ? opt->run : 512;
-    if (!sm::sort_run_ok(*run)) return fail(SM_ERR_ARG, "run must be 256, 512, 1024 or 2048");
+    if (!sm::sort_run_ok(*run, dtype))
+        return fail(SM_ERR_ARG, "run must be 256, 512, 1024, 2048 or (32-bit keys) 4096");
     *tile = pick_tile(dtype, pay, opt);
     int rc = check_tile(dtype, pay, *tile);
     if (rc != SM_OK) return rc;

@@ -18,8 +18,8 @@ struct SortLayout {
     BatchLayout batch;
 };
 
-// Run lengths the run-formation kernel is built for.
-bool sort_run_ok(int run);
+// Run lengths the run-formation kernel is built for (4096 for 32-bit keys).
+bool sort_run_ok(int run, int dtype);
 
 // Number of merge passes after runs of `run` elements: ceil(log2(N / run)).
 int sort_passes(int64_t N, int run);

@@ -126,6 +126,14 @@ hipError_t launch_runs_t(const K* keys, const uint32_t* pay, int64_t N, K* out, 
         case 512: sort_runs_kernel<K, PAY, 512><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
         case 1024: sort_runs_kernel<K, PAY, 1024><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
         case 2048: sort_runs_kernel<K, PAY, 2048><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
+        case 4096:
+            // 32-bit keys only: two buffers of 4096 keys and payloads fill 64 KiB
+            if constexpr (sizeof(K) == 4) {
+                sort_runs_kernel<K, PAY, 4096><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay);
+                break;
+            } else {
+                return hipErrorInvalidValue;
+            }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -135,7 +143,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-bool sort_run_ok(int run) { return run == 256 || run == 512 || run == 1024 || run == 2048; }
+bool sort_run_ok(int run, int dtype) {
+    return run == 256 || run == 512 || run == 1024 || run == 2048 || (run == 4096 && dtype != 2);
+}
 
 int sort_passes(int64_t N, int run) {
     int p = 0;

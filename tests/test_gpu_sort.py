@@ -52,7 +52,7 @@ def test_sort_sizes(dtype, with_pay):
             check_sort(rand_keys(g, N, alpha, dtype), with_pay)
 
 
-@pytest.mark.parametrize("run", [256, 512, 1024, 2048])
+@pytest.mark.parametrize("run", [256, 512, 1024, 2048, 4096])
 def test_sort_run_lengths(run):
     """Every run length and a tiny merge tile give the same bytes."""
     g = np.random.default_rng(run)
