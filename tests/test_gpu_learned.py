@@ -156,6 +156,13 @@ def test_learned_partition_exact():
             assert c[1] == c[0]                       # every walk is refused: all fall back
         if W >= 1 << 40:
             assert c[1] == 0
+    # a network that predicts nothing useful (all parameters zero: every
+    # guess is 0) changes only the work, never the ranks
+    zero = torch.zeros(learned.NPARAM, dtype=torch.float32, device="cuda:0")
+    for W in (0, 64, 1 << 40):
+        xz, yz, hz, cz = learned.partition_learned(keys, n, m, p_a, p_b, zero, zero, 1, 1, W)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(xz), xr) and np.array_equal(host(yz), yr)
     # the ranks drive the merge: output equals the oracle's merge
     ck, _ = sm.merge_pieces(keys, n, m, p_a, p_b, xb, yb)
     torch.cuda.synchronize()
