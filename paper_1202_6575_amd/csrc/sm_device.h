@@ -62,13 +62,21 @@ struct LaneBlocks {
         rcp_c = c > 0 ? __builtin_amdgcn_rcpf((float)c) : 0.0f;
         rcp_q = q > 0 ? __builtin_amdgcn_rcpf((float)q) : 0.0f;
     }
+    // both written with selects, not branches: lanes of a wave disagree on
+    // which side of r they are, and a divergent branch would run both sides
+    // anyway.  start(i) = i*q + min(i, r) is at most len for i <= L.
     __device__ int start(int i) const {
-        if (i >= L) return len;
-        return i < r ? i * c : i * q + r;
+        const int s = i * q + (i < r ? i : r);
+        return s < len ? s : len;
     }
+    // each quotient is evaluated for every k and discarded when it does not
+    // apply (its operands may then be out of fast_div's range: q = 0 only
+    // when every k < len is below rc, and c = 0 only when len = 0)
     __device__ int of(int k) const {
-        if (k >= len) return L;
-        return k < rc ? fast_div(k, c, rcp_c) : fast_div(k - rc, q, rcp_q) + r;
+        const int lo = fast_div(k, c, rcp_c);
+        const int hi = fast_div(k - rc, q, rcp_q) + r;
+        const int blk = k < rc ? lo : hi;
+        return k >= len ? L : blk;
     }
 };
 
@@ -243,8 +251,11 @@ __device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const
         lx -= hx;
         ly -= hy;
     }
-    rx = nx > 0 ? bx + (X[bx] < x ? 1 : 0) : 0;
-    ry = ny > 0 ? by + (!(y < Y[by]) ? 1 : 0) : 0;
+    // an empty side leaves its base at 0 and must not add the last compare;
+    // the compare is masked rather than branched on, so the compiler keeps
+    // both chains in one block and issues their reads together
+    rx = bx + (int)((nx > 0) & (X[bx] < x));
+    ry = by + (int)((ny > 0) & !(y < Y[by]));
 }
 
 template <typename K>
