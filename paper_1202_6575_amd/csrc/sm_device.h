@@ -49,7 +49,9 @@ __device__ __forceinline__ int fast_div(int k, int d, float rd) {
 
 // The same decomposition for the lane level: p = L blocks (a power of two),
 // lengths below 2^22, divisions by the uniform block sizes via fast_div.
-template <int L>
+// SEL picks select-based arithmetic (fewer instructions) over branches
+// (fewer registers live: the payload kernels sit at their register limit).
+template <int L, bool SEL = true>
 struct LaneBlocks {
     int len, q, r, c, rc;
     float rcp_c, rcp_q;
@@ -66,17 +68,27 @@ struct LaneBlocks {
     // which side of r they are, and a divergent branch would run both sides
     // anyway.  start(i) = i*q + min(i, r) is at most len for i <= L.
     __device__ int start(int i) const {
-        const int s = i * q + (i < r ? i : r);
-        return s < len ? s : len;
+        if constexpr (SEL) {
+            const int s = i * q + (i < r ? i : r);
+            return s < len ? s : len;
+        } else {
+            if (i >= L) return len;
+            return i < r ? i * c : i * q + r;
+        }
     }
-    // each quotient is evaluated for every k and discarded when it does not
-    // apply (its operands may then be out of fast_div's range: q = 0 only
-    // when every k < len is below rc, and c = 0 only when len = 0)
+    // one quotient, with divisor and offset picked per lane: k / c below
+    // rc, (k - rc) / q + r from there on (q = 0 only when every k < len is
+    // below rc; for k >= len the quotient is discarded)
     __device__ int of(int k) const {
-        const int lo = fast_div(k, c, rcp_c);
-        const int hi = fast_div(k - rc, q, rcp_q) + r;
-        const int blk = k < rc ? lo : hi;
-        return k >= len ? L : blk;
+        if constexpr (SEL) {
+            const bool lng = k < rc;
+            const int blk =
+                fast_div(lng ? k : k - rc, lng ? c : q, lng ? rcp_c : rcp_q) + (lng ? 0 : r);
+            return k >= len ? L : blk;
+        } else {
+            if (k >= len) return L;
+            return k < rc ? fast_div(k, c, rcp_c) : fast_div(k - rc, q, rcp_q) + r;
+        }
     }
 };
 
@@ -230,13 +242,32 @@ __device__ __forceinline__ int lower_bound_lds(const K* X, int n, K x) {
     return base + (X[base] < x ? 1 : 0);
 }
 
+template <typename K>
+__device__ __forceinline__ int upper_bound_lds(const K* X, int n, K x) {
+    if (n <= 0) return 0;
+    int base = 0;
+    for (int len = n; len > 1;) {
+        const int half = len >> 1;
+        base = !(x < X[base + half]) ? base + half : base;
+        len -= half;
+    }
+    return base + (!(x < X[base]) ? 1 : 0);
+}
+
 // Both lane-level searches at once: lower_bound of x in X[0, nx) and
 // upper_bound of y in Y[0, ny).  The two probe chains are independent, so
 // each step issues both reads before waiting: half the dependent LDS round
 // trips of running them one after the other.
-template <typename K, int STEPS>
+template <typename K, int STEPS, bool TOGETHER>
 __device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const K* Y, int ny, K y,
                                                   int& rx, int& ry) {
+    if constexpr (!TOGETHER) {
+        // one chain after the other: fewer registers live at once (the
+        // payload kernels keep two sets of payload loads in flight as well)
+        rx = nx > 0 ? lower_bound_lds<K>(X, nx, x) : 0;
+        ry = ny > 0 ? upper_bound_lds<K>(Y, ny, y) : 0;
+        return;
+    }
     int bx = 0, by = 0;
     int lx = nx, ly = ny;
     // STEPS >= ceil(log2(max(nx, ny))); once a length reaches 1 its half is
@@ -258,24 +289,12 @@ __device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const
     ry = by + (int)((ny > 0) & !(y < Y[by]));
 }
 
-template <typename K>
-__device__ __forceinline__ int upper_bound_lds(const K* X, int n, K x) {
-    if (n <= 0) return 0;
-    int base = 0;
-    for (int len = n; len > 1;) {
-        const int half = len >> 1;
-        base = !(x < X[base + half]) ? base + half : base;
-        len -= half;
-    }
-    return base + (!(x < X[base]) ? 1 : 0);
-}
-
-template <typename K>
+template <typename K, bool TOGETHER>
 __device__ __forceinline__ void paired_bounds_any(const K* X, int nx, K x, const K* Y, int ny, K y,
                                                   int& rx, int& ry) {
     const int n = nx > ny ? nx : ny;
     if (n <= 4096) {
-        paired_bounds_lds<K, 12>(X, nx, x, Y, ny, y, rx, ry);
+        paired_bounds_lds<K, 12, TOGETHER>(X, nx, x, Y, ny, y, rx, ry);
     } else {
         rx = lower_bound_lds<K>(X, nx, x);
         ry = upper_bound_lds<K>(Y, ny, y);
@@ -581,6 +600,34 @@ __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint
                                                     int ia2, int ib2, int len2, int co2, int cp2) {
     const int len = len1 > len2 ? len1 : len2;
     if (!__any(len > 0)) return;
+    if constexpr (!PAY) {
+        // keys only: walk LDS pointers rather than slot indices, which saves
+        // the index-to-address step on every read
+        const K *pa1 = sKey + ia1, *pb1 = sKey + ib1, *pa2 = sKey + ia2, *pb2 = sKey + ib2;
+        K *po1 = sOut + co1, *po2 = sOut + co2;
+        K ka1 = *pa1, kb1 = *pb1, ka2 = *pa2, kb2 = *pb2;
+        int k = 0;
+        do {
+            const bool t1 = kb1 < ka1;
+            const bool t2 = kb2 < ka2;
+            const K* s1 = t1 ? pb1 : pa1;
+            const K* s2 = t2 ? pb2 : pa2;
+            po1[k] = t1 ? kb1 : ka1;
+            po2[k] = t2 ? kb2 : ka2;
+            const K kn1 = s1[1];
+            const K kn2 = s2[1];
+            pb1 = t1 ? s1 + 1 : pb1;
+            pa1 = t1 ? pa1 : s1 + 1;
+            kb1 = t1 ? kn1 : kb1;
+            ka1 = t1 ? ka1 : kn1;
+            pb2 = t2 ? s2 + 1 : pb2;
+            pa2 = t2 ? pa2 : s2 + 1;
+            kb2 = t2 ? kn2 : kb2;
+            ka2 = t2 ? ka2 : kn2;
+            ++k;
+        } while (__any(k < len));
+        return;
+    }
     K ka1 = sKey[ia1], kb1 = sKey[ib1];
     K ka2 = sKey[ia2], kb2 = sKey[ib2];
     int k = 0;
@@ -680,13 +727,13 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int baseA = p.offA, baseB = p.wa + p.offB;
 
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
-    const LaneBlocks<L> LA(a), LB(b);
+    const LaneBlocks<L, !PAY> LA(a), LB(b);
     {
         const int xt = LA.start(t), yt = LB.start(t);
         // lanes without a block start search with the successor slot's key
         // and discard the result
         int rx, ry;
-        paired_bounds_any<K>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
+        paired_bounds_any<K, !PAY>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
                              sKey[baseB + (yt < b ? yt : b)], rx, ry);
         sXb[t] = xt < a ? rx : b;
         sYb[t] = yt < b ? ry : a;
