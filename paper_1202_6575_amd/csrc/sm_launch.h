@@ -10,6 +10,8 @@ namespace sm {
 constexpr int kMergeThreads = 256;
 // Largest dynamic LDS a merge workgroup may use (gfx950: 160 KiB per CU).
 constexpr uint32_t kMaxLds = 160 * 1024;
+// LDS allocation unit of one workgroup (128 of them make up kMaxLds)
+constexpr uint32_t kLdsGranule = 1280;
 
 // LDS bytes a merge workgroup needs for subproblems of up to cap elements.
 uint32_t merge_lds_bytes(int dtype, bool pay, uint32_t cap);

@@ -7,6 +7,7 @@
 //    writes a descriptor (the five cases in two-select form).
 // K3 merge_persistent_kernel / merge_direct_kernel: the merges, one
 //    workgroup per subproblem at a time (the workgroup merge of sm_device.h).
+#include <atomic>
 #include "sm_device.h"
 #include "sm_launch.h"
 
@@ -370,6 +371,34 @@ static hipError_t allow_big_lds(Kern kern) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
 }
 
+// Workgroups of a persistent merge kernel that fit one compute unit at once.
+// LDS is handed out in granules of kLdsGranule bytes (measured: workgroups
+// with X bytes co-reside k to a CU exactly while k * ceil(X / 1280) <= 128),
+// which the runtime's occupancy calculator does not apply; it still bounds
+// the count by registers and waves.  A grid sized past the true count runs
+// the surplus workgroups as a second, serial wave: each takes a fixed share
+// of the subproblems, so that doubles the time.  Each kernel caches the
+// answer for the last LDS size.
+template <typename Kern>
+static int resident_per_cu(Kern kern, uint32_t lds, std::atomic<uint64_t>& last) {
+    const uint64_t c = last.load(std::memory_order_relaxed);
+    if (c != 0 && (uint32_t)(c >> 32) == lds) return (int)(uint32_t)c;
+    const uint32_t granted = (lds + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+    int n = (int)(kMaxLds / (granted > 0 ? granted : kLdsGranule));
+    int by_regs = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, kern, kMergeThreads, lds) ==
+            hipSuccess &&
+        by_regs >= 1) {
+        if (by_regs < n) n = by_regs;
+    } else {
+        (void)hipGetLastError();
+    }
+    if (n > 8) n = 8;
+    if (n < 1) n = 1;
+    last.store(((uint64_t)lds << 32) | (uint32_t)n, std::memory_order_relaxed);
+    return n;
+}
+
 // Largest subproblem the register-pipelined kernel with R chunks per thread
 // can stage: key chunks <= cap / V + 4 and payload chunks <= cap / 4 + 4 must
 // not exceed R * L.
@@ -392,27 +421,25 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
     const bool whole = (uint64_t)nkeys * sizeof(K) < (1ull << 32) - 4096;
     if constexpr (R <= 5) {
         if (whole) {
-            auto go = [&](auto kern, bool& attr2) -> hipError_t {
+            auto go = [&](auto kern, bool& attr2, std::atomic<uint64_t>& occ) -> hipError_t {
                 if (!attr2) {
                     hipError_t e = allow_big_lds(kern);
                     if (e != hipSuccess) return e;
                     attr2 = true;
                 }
                 const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
-                int per_cu = (int)(kMaxLds / lds);
-                if (per_cu > 8) per_cu = 8;
-                if (per_cu < 1) per_cu = 1;
-                int64_t grid = (int64_t)device_cu_count() * per_cu;
+                int64_t grid = (int64_t)device_cu_count() * resident_per_cu(kern, lds, occ);
                 if (grid > P) grid = P;
                 kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P,
                                                      P_dev, cap);
                 return hipGetLastError();
             };
             static bool attr2 = false;
+            static std::atomic<uint64_t> occ2{0};
             if constexpr (sizeof(K) == 8 && PAY)
-                return go(merge_pipelined_wide_kernel<K, PAY, L, R>, attr2);
+                return go(merge_pipelined_wide_kernel<K, PAY, L, R>, attr2, occ2);
             else
-                return go(merge_pipelined_kernel<K, PAY, L, R>, attr2);
+                return go(merge_pipelined_kernel<K, PAY, L, R>, attr2, occ2);
         }
     }
     auto kern = merge_persistent_kernel<K, PAY, L, R>;
@@ -423,10 +450,8 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
         attr = true;
     }
     const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
-    int per_cu = (int)(kMaxLds / lds);
-    if (per_cu > 8) per_cu = 8;
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)device_cu_count() * per_cu;
+    static std::atomic<uint64_t> occ{0};
+    int64_t grid = (int64_t)device_cu_count() * resident_per_cu(kern, lds, occ);
     if (grid > P) grid = P;
     kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
     return hipGetLastError();
