@@ -719,7 +719,11 @@ __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint3
 // the whole workgroup after a barrier that follows commit / stage_direct;
 // ends after a barrier, with output k in sOut[offC + k] (and, with payloads,
 // its payload in sIdx[offCP + k]).  The staging buffers are free afterwards.
-template <typename K, bool PAY, int L>
+// LEAN = the caller has registers to spare: both lane-level searches run
+// together and lane blocks use select arithmetic (otherwise the searches run
+// one after the other and the block arithmetic branches, to stay within the
+// payload kernels' register budget).
+template <typename K, bool PAY, int L, bool LEAN = !PAY>
 __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, const uint32_t* sPay,
                                             K* sOut, uint32_t* sIdx, int* sXb, int* sYb) {
     const int t = threadIdx.x;
@@ -727,13 +731,13 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int baseA = p.offA, baseB = p.wa + p.offB;
 
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
-    const LaneBlocks<L, !PAY> LA(a), LB(b);
+    const LaneBlocks<L, LEAN> LA(a), LB(b);
     {
         const int xt = LA.start(t), yt = LB.start(t);
         // lanes without a block start search with the successor slot's key
         // and discard the result
         int rx, ry;
-        paired_bounds_any<K, !PAY>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
+        paired_bounds_any<K, LEAN>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
                              sKey[baseB + (yt < b ? yt : b)], rx, ry);
         sXb[t] = xt < a ? rx : b;
         sYb[t] = yt < b ? ry : a;

@@ -176,7 +176,9 @@ __device__ __forceinline__ void merge_pipelined(
         __syncthreads();
         if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
         prefetch_whole<K, PAY, L, R>(nn, rkeys, rpay, rk, rp);
-        if (cur.s > 0) merge_lanes<K, PAY, L>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
+        if (cur.s > 0)
+            merge_lanes<K, PAY, L, (!PAY || R <= 3)>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx,
+                                                    sp.sXb, sp.sYb);
         prev = cur;
         cur = nxt;
         nxt = nn;
@@ -465,6 +467,13 @@ static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_
     const K* keys = static_cast<const K*>(keys_v);
     K* out = static_cast<K*>(out_v);
     if (P <= 0) return hipSuccess;
+    // 32-bit keys with payloads at the default block lengths need only three
+    // chunks per thread: the freed registers pay for the lean lane level
+    if constexpr (PAY && sizeof(K) == 4) {
+        if (fits_regs<K, PAY>(cap, 3))
+            return launch_persistent<K, PAY, 3>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev,
+                                                cap, st);
+    }
     if (fits_regs<K, PAY>(cap, 5))
         return launch_persistent<K, PAY, 5>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap,
                                             st);

@@ -137,7 +137,10 @@ def test_tiling_independence():
     A, B = rand_sorted(g, 50_000, 64, np.int32), rand_sorted(g, 30_000, 64, np.int32)
     pa, pb = datagen.source_tag_payloads(len(A), len(B))
     ref = run_merge(A, B, pa, pb)
-    for kw in [dict(tile=1), dict(tile=16), dict(tile=1000), dict(tile=3072), dict(tile=4096),
+    # 1526 and 1528 sit on either side of the largest payload block length
+    # that three register chunks per thread can stage
+    for kw in [dict(tile=1), dict(tile=16), dict(tile=1000), dict(tile=1526), dict(tile=1528),
+               dict(tile=3072), dict(tile=4096),
                dict(p_a=3, p_b=7),
                dict(p_a=1000, p_b=1)]:
         flush(f"tiling {kw}")
