@@ -396,8 +396,16 @@ __device__ __forceinline__ SegPlan make_plan(const PieceDesc& d) {
     p.esB = (p.offB + p.b) % V;
     p.offPA = (int)(d.ka0 & 3);
     p.offPB = (int)(d.kb0 & 3);
-    p.ncpa = PAY ? (p.offPA + p.a + 3) / 4 : 0;
-    p.ncpb = PAY ? (p.offPB + p.b + 3) / 4 : 0;
+    if constexpr (PAY && sizeof(K) == 4) {
+        // 32-bit keys: the payload windows take the key windows' geometry
+        // slot for slot (successor chunk included), so the payload of the
+        // key in slot i sits in payload slot i
+        p.ncpa = p.nca;
+        p.ncpb = p.ncb;
+    } else {
+        p.ncpa = PAY ? (p.offPA + p.a + 3) / 4 : 0;
+        p.ncpb = PAY ? (p.offPB + p.b + 3) / 4 : 0;
+    }
     p.waP = p.ncpa * 4;
     p.c0 = d.out0;
     p.offC = (int)(d.out0 & (V - 1));
@@ -594,17 +602,21 @@ __device__ __forceinline__ void lane_merge_uniform(const K* sKey, K* sOut, uint3
 // reads are independent, so each step waits once for both.  Same uniform
 // trip-count rule as lane_merge_uniform (the larger of the two lengths,
 // maximised over the wave).
-template <typename K, bool PAY>
+template <typename K, bool PAY, bool DIRECT>
 __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint32_t* sIdx,
-                                                    int ia1, int ib1, int len1, int co1, int cp1,
-                                                    int ia2, int ib2, int len2, int co2, int cp2) {
+                                                    int dPay, int ia1, int ib1, int len1, int co1,
+                                                    int cp1, int ia2, int ib2, int len2, int co2,
+                                                    int cp2) {
     const int len = len1 > len2 ? len1 : len2;
     if (!__any(len > 0)) return;
-    if constexpr (!PAY) {
-        // keys only: walk LDS pointers rather than slot indices, which saves
-        // the index-to-address step on every read
+    if constexpr (!PAY || DIRECT) {
+        // walk LDS pointers rather than slot indices, which saves the
+        // index-to-address step on every read; with DIRECT payloads the
+        // payload of the taken key is read dPay slots further on
         const K *pa1 = sKey + ia1, *pb1 = sKey + ib1, *pa2 = sKey + ia2, *pb2 = sKey + ib2;
         K *po1 = sOut + co1, *po2 = sOut + co2;
+        uint32_t* pp1 = DIRECT ? sIdx + cp1 : nullptr;
+        uint32_t* pp2 = DIRECT ? sIdx + cp2 : nullptr;
         K ka1 = *pa1, kb1 = *pb1, ka2 = *pa2, kb2 = *pb2;
         int k = 0;
         do {
@@ -614,6 +626,10 @@ __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint
             const K* s2 = t2 ? pb2 : pa2;
             po1[k] = t1 ? kb1 : ka1;
             po2[k] = t2 ? kb2 : ka2;
+            if constexpr (DIRECT) {
+                pp1[k] = reinterpret_cast<const uint32_t*>(s1)[dPay];
+                pp2[k] = reinterpret_cast<const uint32_t*>(s2)[dPay];
+            }
             const K kn1 = s1[1];
             const K kn2 = s2[1];
             pb1 = t1 ? s1 + 1 : pb1;
@@ -696,9 +712,9 @@ struct OddEvenMerge {
 };
 
 // Bounds-checked form: each lane stops after its own la + lb outputs.
-template <typename K, bool PAY>
-__device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint32_t* sIdx, int ia,
-                                                   int la, int ib, int lb, int co, int cp) {
+template <typename K, bool PAY, bool DIRECT>
+__device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint32_t* sIdx, int dPay,
+                                                   int ia, int la, int ib, int lb, int co, int cp) {
     const int len = la + lb;
     const int ea = ia + la, eb = ib + lb;
     K ka = sKey[ia];
@@ -707,7 +723,8 @@ __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint3
         const bool takeB = (ib < eb) && (ia >= ea || kb < ka);
         const int src = takeB ? ib : ia;
         sOut[co + k] = takeB ? kb : ka;
-        if (PAY) sIdx[cp + k] = (uint32_t)src;
+        if constexpr (DIRECT) sIdx[cp + k] = reinterpret_cast<const uint32_t*>(sKey)[src + dPay];
+        else if (PAY) sIdx[cp + k] = (uint32_t)src;
         const int nxt = src + 1;
         const K kn = sKey[nxt];
         if (takeB) { ib = nxt; kb = kn; }
@@ -729,6 +746,11 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int t = threadIdx.x;
     const int a = p.a, b = p.b, s = p.s;
     const int baseA = p.offA, baseB = p.wa + p.offB;
+    // 32-bit keys: payload slot = key slot + dPay (the payload windows share
+    // the key windows' geometry), so the merges write payloads themselves;
+    // otherwise they write key slots and a gather pass follows
+    constexpr bool DIRECT = PAY && sizeof(K) == 4;
+    const int dPay = DIRECT ? (int)(sPay - reinterpret_cast<const uint32_t*>(sKey)) : 0;
 
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
     const LaneBlocks<L, LEAN> LA(a), LB(b);
@@ -768,19 +790,21 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int la3 = ok3 ? p3.a_hi - p3.a_lo : 0, lb3 = ok3 ? p3.b_hi - p3.b_lo : 0;
     const int la4 = ok4 ? p4.a_hi - p4.a_lo : 0, lb4 = ok4 ? p4.b_hi - p4.b_lo : 0;
     if (fast) {
-        lane_merge_uniform2<K, PAY>(sKey, sOut, sIdx, baseA + p3.a_lo, baseB + p3.b_lo, la3 + lb3,
-                                    p.offC + p3.c_off, p.offCP + p3.c_off, baseA + p4.a_lo,
-                                    baseB + p4.b_lo, la4 + lb4, p.offC + p4.c_off,
-                                    p.offCP + p4.c_off);
+        lane_merge_uniform2<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, baseA + p3.a_lo,
+                                            baseB + p3.b_lo, la3 + lb3, p.offC + p3.c_off,
+                                            p.offCP + p3.c_off, baseA + p4.a_lo, baseB + p4.b_lo,
+                                            la4 + lb4, p.offC + p4.c_off, p.offCP + p4.c_off);
     } else {
-        lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + p3.a_lo, la3, baseB + p3.b_lo, lb3,
-                                   p.offC + p3.c_off, p.offCP + p3.c_off);
-        lane_merge_checked<K, PAY>(sKey, sOut, sIdx, baseA + p4.a_lo, la4, baseB + p4.b_lo, lb4,
-                                   p.offC + p4.c_off, p.offCP + p4.c_off);
+        lane_merge_checked<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, baseA + p3.a_lo, la3,
+                                           baseB + p3.b_lo, lb3, p.offC + p3.c_off,
+                                           p.offCP + p3.c_off);
+        lane_merge_checked<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, baseA + p4.a_lo, la4,
+                                           baseB + p4.b_lo, lb4, p.offC + p4.c_off,
+                                           p.offCP + p4.c_off);
     }
     __syncthreads();
 
-    if (PAY) {
+    if (PAY && !DIRECT) {
         // gather: key slot of each output -> its payload (same element in the
         // payload window geometry), in place
         for (int k = t; k < s; k += L) {
