@@ -268,25 +268,30 @@ __device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const
         ry = ny > 0 ? upper_bound_lds<K>(Y, ny, y) : 0;
         return;
     }
-    int bx = 0, by = 0;
+    // the bases are LDS pointers: a step is one add (probe address), the
+    // read, the compare and one select
+    const K* bx = X;
+    const K* by = Y;
     int lx = nx, ly = ny;
     // STEPS >= ceil(log2(max(nx, ny))); once a length reaches 1 its half is
     // 0 and the step re-reads the same slot without moving
 #pragma unroll
     for (int i = 0; i < STEPS; ++i) {
         const int hx = lx >> 1, hy = ly >> 1;
-        const K vx = X[bx + hx];
-        const K vy = Y[by + hy];
-        bx = vx < x ? bx + hx : bx;
-        by = !(y < vy) ? by + hy : by;
+        const K* px = bx + hx;
+        const K* py = by + hy;
+        const K vx = *px;
+        const K vy = *py;
+        bx = vx < x ? px : bx;
+        by = !(y < vy) ? py : by;
         lx -= hx;
         ly -= hy;
     }
-    // an empty side leaves its base at 0 and must not add the last compare;
-    // the compare is masked rather than branched on, so the compiler keeps
-    // both chains in one block and issues their reads together
-    rx = bx + (int)((nx > 0) & (X[bx] < x));
-    ry = by + (int)((ny > 0) & !(y < Y[by]));
+    // an empty side leaves its base at the start and must not add the last
+    // compare; the compare is masked rather than branched on, so the
+    // compiler keeps both chains in one block and issues their reads together
+    rx = (int)(bx - X) + (int)((nx > 0) & (*bx < x));
+    ry = (int)(by - Y) + (int)((ny > 0) & !(y < *by));
 }
 
 template <typename K, bool TOGETHER>
