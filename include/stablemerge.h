@@ -306,6 +306,28 @@ SM_API int stable_merge_partition_learned(const void *keys, int64_t n, int64_t m
                                           int64_t window, int64_t *xbar, int64_t *ybar,
                                           uint64_t *hist, uint64_t *counters, void *stream);
 
+/*
+ * The whole stable merge with learned cross ranks: the partition of
+ * stable_merge_partition_learned with blocks of `block` elements per side
+ * (p_a = ceil(n / block), p_b = ceil(m / block), at least 1 each), then
+ * Steps 3-4 as stable_merge_pieces.  The output is the unique stable merge,
+ * byte for byte what stable_merge writes, whatever the models predict.
+ * keys, payloads and outputs follow the rules of stable_merge; model_b /
+ * model_a, step0_a / step0_b, window, hist and counters those of
+ * stable_merge_partition_learned (the caller zeroes hist and counters).
+ * 1 <= block <= 2^20.  ws must hold stable_merge_learned_workspace_bytes()
+ * bytes (the cross ranks, then the merge's workspace).
+ */
+SM_API int stable_merge_learned(const void *keys, const uint32_t *payloads, int64_t n, int64_t m,
+                                void *out_keys, uint32_t *out_payloads, int dtype,
+                                const float *model_b, const float *model_a, int64_t step0_a,
+                                int64_t step0_b, int64_t block, int64_t window, uint64_t *hist,
+                                uint64_t *counters, void *ws, size_t ws_bytes, void *stream);
+
+/* Device workspace bytes of stable_merge_learned (0 on bad arguments). */
+SM_API size_t stable_merge_learned_workspace_bytes(int64_t n, int64_t m, int64_t block, int dtype,
+                                                   int has_payload);
+
 #ifdef __cplusplus
 }
 #endif

@@ -519,4 +519,41 @@ int stable_merge_partition_learned(const void* keys, int64_t n, int64_t m, int64
     return e == hipSuccess ? SM_OK : hip_fail(e, "learned partition launch");
 }
 
+size_t stable_merge_learned_workspace_bytes(int64_t n, int64_t m, int64_t block, int dtype,
+                                            int has_payload) {
+    if (!dtype_ok(dtype) || n < 0 || m < 0 || block < 1 || block > (1ll << 20)) return 0;
+    const int64_t p_a = n > 0 ? (n + block - 1) / block : 1;
+    const int64_t p_b = m > 0 ? (m + block - 1) / block : 1;
+    const size_t merge_ws = stable_merge_pieces_workspace_bytes(n, m, p_a, p_b, dtype, has_payload);
+    if (merge_ws == 0 && n + m > 0) return 0;
+    return ranks_bytes(p_a, p_b) + merge_ws;
+}
+
+int stable_merge_learned(const void* keys, const uint32_t* payloads, int64_t n, int64_t m,
+                         void* out_keys, uint32_t* out_payloads, int dtype, const float* model_b,
+                         const float* model_a, int64_t step0_a, int64_t step0_b, int64_t block,
+                         int64_t window, uint64_t* hist, uint64_t* counters, void* ws,
+                         size_t ws_bytes, void* stream) {
+    int rc = check_sizes(n, m, dtype);
+    if (rc != SM_OK) return rc;
+    if (block < 1 || block > (1ll << 20)) return fail(SM_ERR_ARG, "1 <= block <= 2^20 required");
+    if (n + m == 0) return SM_OK;
+    rc = check_buffers(keys, payloads, n + m, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    const size_t need = stable_merge_learned_workspace_bytes(n, m, block, dtype, payloads != nullptr);
+    if (need == 0) return fail(SM_ERR_ARG, "sizes not supported");
+    rc = check_ws(ws, ws_bytes, need);
+    if (rc != SM_OK) return rc;
+    const int64_t p_a = n > 0 ? (n + block - 1) / block : 1;
+    const int64_t p_b = m > 0 ? (m + block - 1) / block : 1;
+    int64_t* xbar = static_cast<int64_t*>(ws);
+    int64_t* ybar = xbar + (p_a + 1);
+    const size_t off = ranks_bytes(p_a, p_b);
+    rc = stable_merge_partition_learned(keys, n, m, p_a, p_b, dtype, model_b, model_a, step0_a,
+                                        step0_b, window, xbar, ybar, hist, counters, stream);
+    if (rc != SM_OK) return rc;
+    return stable_merge_pieces(keys, payloads, n, m, p_a, p_b, xbar, ybar, out_keys, out_payloads,
+                               dtype, static_cast<char*>(ws) + off, ws_bytes - off, stream);
+}
+
 }  // extern "C"

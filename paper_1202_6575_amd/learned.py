@@ -44,6 +44,11 @@ _lib.stable_merge_rank_search.argtypes = [_vp, _i64, _vp, _i64, _i32, _i32, _vp,
 _lib.stable_merge_partition_learned.restype = _i32
 _lib.stable_merge_partition_learned.argtypes = [_vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _i64,
                                                 _i64, _i64, _vp, _vp, _vp, _vp, _vp]
+_lib.stable_merge_learned.restype = _i32
+_lib.stable_merge_learned.argtypes = [_vp, _vp, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _i64, _i64,
+                                      _i64, _i64, _vp, _vp, _vp, _sz, _vp]
+_lib.stable_merge_learned_workspace_bytes.restype = _sz
+_lib.stable_merge_learned_workspace_bytes.argtypes = [_i64, _i64, _i64, _i32, _i32]
 
 
 def _f32_params(p):
@@ -152,3 +157,37 @@ def partition_learned(keys, n, m, p_a, p_b, model_b, model_a, step0_a=1, step0_b
                                                int(step0_b), int(window), _ptr(xbar), _ptr(ybar),
                                                _ptr(hist), _ptr(counters), _stream_ptr(stream)))
     return xbar, ybar, hist, counters
+
+
+def merge_learned(keys, n, m, model_b, model_a, step0_a=1, step0_b=1, block=16, window=256,
+                  payloads=None, *, out_keys=None, out_payloads=None, hist=None, counters=None,
+                  workspace=None, stream=None):
+    """The whole stable merge of keys = A (n) ‖ B (m) with learned cross
+    ranks at blocks of `block` elements per side.  Returns (out_keys,
+    out_payloads, hist, counters); the output is the unique stable merge
+    whatever the models predict."""
+    _f32_params(model_b)
+    _f32_params(model_a)
+    _require_device(keys, payloads, out_keys, out_payloads, hist, counters, workspace)
+    dev = keys.device
+    code = _dtype_code(keys)
+    if workspace is None:
+        need = int(_lib.stable_merge_learned_workspace_bytes(n, m, int(block), code,
+                                                             int(payloads is not None)))
+        if need == 0:
+            raise SMError(-1, "stable_merge_learned: unsupported sizes or block")
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if out_keys is None:
+        out_keys = torch.empty(n + m, dtype=keys.dtype, device=dev)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(n + m, dtype=torch.uint32, device=dev)
+    if hist is None:
+        hist = torch.zeros(HIST_BINS, dtype=torch.uint64, device=dev)
+    if counters is None:
+        counters = torch.zeros(4, dtype=torch.uint64, device=dev)
+    _check(_lib.stable_merge_learned(_ptr(keys), _ptr(payloads), n, m, _ptr(out_keys),
+                                     _ptr(out_payloads), code, _ptr(model_b), _ptr(model_a),
+                                     int(step0_a), int(step0_b), int(block), int(window),
+                                     _ptr(hist), _ptr(counters), _ptr(workspace),
+                                     workspace.numel(), _stream_ptr(stream)))
+    return out_keys, out_payloads, hist, counters

@@ -111,3 +111,24 @@ def test_batched_error_paths(sm):
 
 def test_version(sm):
     assert sm._lib.sm_version() >= 100
+
+
+def test_learned_merge_error_paths(sm):
+    from paper_1202_6575_amd import learned  # noqa: F401  (sets the argument types)
+    f = sm._lib.stable_merge_learned
+
+    def call(keys=0x10000, pay=None, n=100, m=100, out=0x20000, opay=None, dtype=1, block=16,
+             ws=0x30000, ws_bytes=1 << 20):
+        return f(keys, pay, n, m, out, opay, dtype, 0x40000, 0x50000, 1, 1, block, 256, 0x60000,
+                 0x70000, ws, ws_bytes, None)
+
+    assert call(dtype=9) == -2
+    assert call(n=-1) == -1
+    assert call(block=0) == -1
+    assert call(block=(1 << 20) + 1) == -1
+    assert call(out=0x10000 + 64) == -3                            # out overlaps keys
+    assert call(ws_bytes=16) == -4
+    assert call(n=0, m=0) == 0                                      # nothing to do
+    q = sm._lib.stable_merge_learned_workspace_bytes
+    assert q(100, 100, 0, 1, 0) == 0
+    assert q(100, 100, 16, 1, 0) > 0 and q(100, 100, 16, 1, 1) >= q(100, 100, 16, 1, 0)

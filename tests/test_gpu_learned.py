@@ -169,6 +169,54 @@ def test_learned_partition_exact():
     assert np.array_equal(host(ck), oracle.merge(A, B)[0])
 
 
+def test_merge_learned_end_to_end():
+    """The composite entry point: learned partition + Steps 3-4 give the
+    oracle's stable merge (keys and payloads) for several block lengths,
+    windows and a model that predicts nothing useful."""
+    n, m = 300_001, 200_003
+    A = datagen.lognormal_mixture(n, 41)
+    B = datagen.lognormal_mixture(m, 42)
+    pb, lb, pa, la = train_pair(A, B, samples=1 << 14, steps=200)
+    keys = dev(np.concatenate([A, B]))
+    pay = np.arange(n + m, dtype=np.uint32)
+    rk, rp = oracle.merge(A, B, pay[:n], pay[n:])
+    zero = torch.zeros(learned.NPARAM, dtype=torch.float32, device="cuda:0")
+    s0a, s0b = learned.step0_from_loss(lb, m), learned.step0_from_loss(la, n)
+    for (mb, ma, sa, sb, block, W) in [(pb, pa, s0a, s0b, 16, 1 << 40), (pb, pa, 1, 1, 16, 64),
+                                       (pb, pa, s0a, s0b, 1, 1 << 20), (pb, pa, 1, 1, 64, 256),
+                                       (zero, zero, 1, 1, 16, 0), (pb, pa, 1, 1, 5000, 256)]:
+        flush(f"merge_learned block={block} W={W} step0=({sa},{sb})")
+        ok, op, hist, cnt = learned.merge_learned(keys, n, m, mb, ma, sa, sb, block, W, dev(pay))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ok), rk) and np.array_equal(host(op), rp)
+        c = host(cnt).astype(np.int64)
+        pa_, pb_ = -(-n // block), -(-m // block)
+        assert c[0] == pa_ + pb_ and host(hist).astype(np.int64).sum() == c[0]
+        okk, _, _, _ = learned.merge_learned(keys, n, m, mb, ma, sa, sb, block, W)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(okk), rk)
+    # empty sides
+    for (nn, mm) in [(0, 1000), (1000, 0), (0, 0), (1, 1)]:
+        A2, B2 = A[:nn], B[:mm]
+        k2 = dev(np.concatenate([A2, B2])) if nn + mm else dev(np.zeros(1, np.uint32))
+        ok, _, _, _ = learned.merge_learned(k2, nn, mm, pb, pa, 1, 1, 16, 256)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ok)[:nn + mm], oracle.merge(A2, B2)[0])
+
+
+def test_merge_learned_errors():
+    keys = dev(np.arange(100, dtype=np.uint32))
+    zero = torch.zeros(learned.NPARAM, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(sm.SMError):
+        learned.merge_learned(keys, 50, 50, zero, zero, 1, 1, 0, 256)
+    with pytest.raises(sm.SMError):
+        learned.merge_learned(keys, 50, 50, zero, zero, 1, 1, 16, 256, out_keys=keys)
+    small = torch.empty(8, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(sm.SMError) as e:
+        learned.merge_learned(keys, 50, 50, zero, zero, 1, 1, 16, 256, workspace=small)
+    assert e.value.code == -4
+
+
 def test_trained_network_gain():
     """On the log-normal mixture, the trained network brings the search to
     fewer probes per rank than the plain binary search (floor(log2 len) + 1
