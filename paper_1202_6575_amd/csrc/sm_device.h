@@ -274,7 +274,9 @@ __device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const
     const K* by = Y;
     int lx = nx, ly = ny;
     // STEPS >= ceil(log2(max(nx, ny))); once a length reaches 1 its half is
-    // 0 and the step re-reads the same slot without moving
+    // 0 and the step re-reads the same slot without moving.  (A count taken
+    // from the lengths saves steps on small segments but, as a loop the
+    // compiler cannot unroll, measured slower on full ones.)
 #pragma unroll
     for (int i = 0; i < STEPS; ++i) {
         const int hx = lx >> 1, hy = ly >> 1;
@@ -290,8 +292,12 @@ __device__ __forceinline__ void paired_bounds_lds(const K* X, int nx, K x, const
     // an empty side leaves its base at the start and must not add the last
     // compare; the compare is masked rather than branched on, so the
     // compiler keeps both chains in one block and issues their reads together
-    rx = (int)(bx - X) + (int)((nx > 0) & (*bx < x));
-    ry = (int)(by - Y) + (int)((ny > 0) & !(y < *by));
+    // slot index = byte distance / sizeof(K), in 32-bit arithmetic (the low
+    // half of a generic LDS address is the LDS offset)
+    const uint32_t dx = (uint32_t)(uintptr_t)bx - (uint32_t)(uintptr_t)X;
+    const uint32_t dy = (uint32_t)(uintptr_t)by - (uint32_t)(uintptr_t)Y;
+    rx = (int)(dx / sizeof(K)) + (int)((nx > 0) & (*bx < x));
+    ry = (int)(dy / sizeof(K)) + (int)((ny > 0) & !(y < *by));
 }
 
 template <typename K, bool TOGETHER>
