@@ -326,10 +326,12 @@ __device__ __forceinline__ void paired_bounds_any(const K* X, int nx, K x, const
 //   sKey[wa, wa + nb*V)    B window, B[j] at slot wa + offB + j, successor
 //                          at wa + offB + b
 //   sPay                   payload windows, A[i] at offPA + i, B[j] at
-//                          waP + offPB + j
+//                          waP + offPB + j (for 32-bit keys the same slots
+//                          as the keys: offPA = offA, waP = wa, offPB = offB)
 //   sOut                   merged keys, output k at offC + k
-//   sIdx                   payload case: key slot of output k at offCP + k,
-//                          then (after the gather) its payload
+//   sIdx                   payloads of the outputs, output k at offCP + k
+//                          (64-bit keys: first the key slot of output k,
+//                          replaced by its payload in a gather pass)
 //   sXb[L+1], sYb[L+1]     lane-level cross ranks
 //
 // Lane level: the workgroup is p = L processing elements.  The A and B
@@ -576,43 +578,20 @@ __device__ __forceinline__ void stage_direct(const SegPlan& p, const K* keys, ui
     }
 }
 
-// Sequential stable merge of one lane subproblem: A slots from ia, B slots
-// from ib, la + lb outputs at slots from co.
+// Sequential stable merges of a lane's two subproblems (A slots from ia, B
+// slots from ib, len outputs at slots from co, payload outputs from cp), in
+// one loop: the two chains of dependent LDS reads are independent, so each
+// step waits once for both.
 //
 // Uniform form (sentinels valid): every lane of the wave runs the same number
-// of steps, the largest la + lb in the wave.  A lane that is done keeps
-// merging: its start (ia, ib) is a prefix state of the stable merge (the
-// outputs before c_off are exactly A[0, a_lo) and B[0, b_lo)), so its extra
-// outputs are the true next outputs -- the same values the lanes owning those
-// slots write -- or lie past the subproblem, in slack slots nobody reads.
-// Reads stay valid until the lane has output the whole subproblem: the
-// successors stand in for the element after each segment.
-template <typename K, bool PAY>
-__device__ __forceinline__ void lane_merge_uniform(const K* sKey, K* sOut, uint32_t* sIdx, int ia,
-                                                   int ib, int len, int co, int cp) {
-    if (!__any(len > 0)) return;
-    K ka = sKey[ia];
-    K kb = sKey[ib];
-    int k = 0;
-    do {
-        const bool takeB = kb < ka;
-        const int src = takeB ? ib : ia;
-        sOut[co + k] = takeB ? kb : ka;
-        if (PAY) sIdx[cp + k] = (uint32_t)src;
-        const int nxt = src + 1;
-        const K kn = sKey[nxt];
-        ib = takeB ? nxt : ib;
-        ia = takeB ? ia : nxt;
-        kb = takeB ? kn : kb;
-        ka = takeB ? ka : kn;
-        ++k;
-    } while (__any(k < len));
-}
-
-// Two lane subproblems merged in one loop: the two chains of dependent LDS
-// reads are independent, so each step waits once for both.  Same uniform
-// trip-count rule as lane_merge_uniform (the larger of the two lengths,
-// maximised over the wave).
+// of steps, the largest of the two lengths maximised over the wave.  A lane
+// that is done keeps merging: its start (ia, ib) is a prefix state of the
+// stable merge (the outputs before its c_off are exactly A[0, a_lo) and
+// B[0, b_lo)), so its extra outputs are the true next outputs -- the same
+// values the lanes owning those slots write -- or lie past the subproblem, in
+// slack slots nobody reads.  Reads stay valid until the lane has output the
+// whole subproblem: the successors stand in for the element after each
+// segment.
 template <typename K, bool PAY, bool DIRECT>
 __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint32_t* sIdx,
                                                     int dPay, int ia1, int ib1, int len1, int co1,
@@ -827,9 +806,8 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     }
 }
 
-// Write-back of merged outputs: aligned 16-byte stores for whole chunks,
-// element stores at the two partial ends.  Reads only sOut / sIdx, so it
-// may run after the staging buffers have been refilled.  RW = number of
+// One output array of a subproblem, LDS -> HBM: aligned 16-byte stores for
+// whole chunks, element stores at the two partial ends.  RW = number of
 // output chunks per thread, unrolled (0 = a loop, for large subproblems).
 template <typename E, int L, int RW>
 __device__ __forceinline__ void write_out(const E* sArr, int off, int s, E* base_out) {
