@@ -280,9 +280,12 @@ SM_API int sm_rank_model_train(const void *X, int64_t len, const void *Q, int64_
  * (device int64, clamped to [0, len]): rank_low (is_high = 0) or rank_high.
  * The search probes the guess g, then X[g +- step0], X[g +- 2 step0], ...
  * away from g until the rank is bracketed (or the array ends), then bisects
- * the bracket; a step beyond `window` abandons the walk for the plain binary
- * search over [0, len].  ranks[i] (int64) is always exact; probes[i] (int32:
- * reads of X) and fallback[i] (int32 0/1) are optional (NULL to skip).
+ * the bracket [lo, hi] of possible ranks, each read splitting it at the
+ * number m in (lo, hi] with the most trailing zero bits (the rank is >= m
+ * exactly when X[m - 1] is below x, or not above it for rank_high); a step
+ * beyond `window` abandons the walk for the same bisection of [0, len].
+ * ranks[i] (int64) is always exact; probes[i] (int32: reads of X) and
+ * fallback[i] (int32 0/1) are optional (NULL to skip).
  * step0 >= 1, 0 <= window <= 2^40.
  */
 SM_API int stable_merge_rank_search(const void *X, int64_t len, const void *queries, int64_t q,

@@ -459,9 +459,10 @@ void orc_sort(void *keys, uint32_t *pay, int64_t N, int64_t run_len,
  * Let pred(t) be "X[t] < x" (low) or "X[t] <= x" (high); the rank is the
  * number of t with pred(t) true.  The search probes g, then moves away from
  * g in steps of step0, 2 step0, 4 step0, ... until the rank is bracketed,
- * then binary searches the bracket.  If a step larger than window would be
- * needed, it gives up and runs the plain binary search over [0, len]
- * instead (*fallback = 1).  *probes counts every element of X that is read.
+ * then binary searches the bracket, splitting it at aligned points (below).
+ * If a step larger than window would be needed, it gives up and binary
+ * searches all of [0, len] instead (*fallback = 1).  *probes counts every
+ * element of X that is read.
  * step0 >= 1 (the initial step is a free choice of the search: a predictor
  * whose typical error is e starts near e instead of 1).
  */
@@ -505,10 +506,17 @@ full:
     lo = 0;
     hi = len;
 bisect:
+    /* The rank lies in [lo, hi].  Each probe splits the bracket at the
+     * number m in (lo, hi] with the most trailing zero bits (the top bit in
+     * which lo and hi differ set, the bits below it clear): the rank is >= m
+     * exactly when X[m - 1] satisfies the predicate.  Split points are
+     * aligned, so searches with nearby brackets probe the same elements. */
     while (lo < hi) {
-        int64_t mid = lo + (hi - lo) / 2;
-        if (PRED(mid)) lo = mid + 1;
-        else hi = mid;
+        int h = 63;
+        while (!(((uint64_t)lo ^ (uint64_t)hi) >> h & 1)) h--;
+        int64_t m = (int64_t)(((uint64_t)hi >> h) << h);
+        if (PRED(m - 1)) lo = m;
+        else hi = m - 1;
     }
 #undef PRED
     *probes = np;

@@ -59,8 +59,9 @@ __device__ __forceinline__ int64_t predict(const float* __restrict__ P, float ph
 
 // Bounded exponential search for the rank of x in X[0, len): probe the
 // guess g, then step away from it by step0, 2 step0, 4 step0, ... until the
-// rank is bracketed (or the array ends), then bisect the bracket.  A step
-// beyond `window` abandons the walk for the binary search over [0, len].
+// rank is bracketed (or the array ends), then bisect the bracket at aligned
+// points.  A step beyond `window` abandons the walk for the same bisection
+// of all of [0, len].
 // Low: pred(t) = X[t] < x (rank_low); high: pred(t) = X[t] <= x (rank_high);
 // the rank is the number of t with pred(t).  `probes` counts reads of X.
 template <typename K, bool HIGH>
@@ -102,10 +103,28 @@ __device__ __forceinline__ int64_t bounded_search(const K* __restrict__ X, int64
         lo = 0;
         hi = len;
     }
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (pred(mid)) lo = mid + 1;
-        else hi = mid;
+    // the rank is in [lo, hi]: split at the number in (lo, hi] with the most
+    // trailing zero bits (the top bit in which lo and hi differ set, the bits
+    // below it clear); the rank is >= m exactly when X[m - 1] satisfies the
+    // predicate.  The split points are aligned, so the lanes of a wave, whose
+    // brackets overlap, read the same elements until their brackets part.
+    if (len < (int64_t)1 << 31) {
+        // the same splits in 32-bit arithmetic (lo, hi <= len)
+        uint32_t l32 = (uint32_t)lo, h32 = (uint32_t)hi;
+        while (l32 < h32) {
+            const int h = 31 - __clz((int)(l32 ^ h32));
+            const uint32_t m = (h32 >> h) << h;
+            if (pred((int64_t)(m - 1))) l32 = m;
+            else h32 = m - 1;
+        }
+        lo = l32;
+    } else {
+        while (lo < hi) {
+            const int h = 63 - __clzll((long long)((uint64_t)lo ^ (uint64_t)hi));
+            const int64_t m = (int64_t)(((uint64_t)hi >> h) << h);
+            if (pred(m - 1)) lo = m;
+            else hi = m - 1;
+        }
     }
     probes = np;
     fell_back = fb;
@@ -334,41 +353,59 @@ __global__ __launch_bounds__(256) void learned_partition_kernel(
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) sh[i] = 0;
     if (threadIdx.x < 3) sc[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const K* A = keys;
     const K* B = keys + n;
-    bool searched = false, fb = false;
-    int np = 0;
-    int64_t err = 0;
-    if (t <= p_a) {
-        const int64_t xi = Blocks<int64_t>(n, p_a).start(t);
-        int64_t r = m;
-        if (xi < n) {
-            const K x = A[xi];
-            const int64_t g = predict(model_b, feature(x), m);
-            r = bounded_search<K, false>(B, m, x, g, step0_a, window, np, fb);
-            err = g - r;
-            searched = true;
+    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
+    // counts of this thread's searches, summed per wave and per workgroup
+    // before they reach the device counters (every search of the grid
+    // adding to the same three words would serialise on them)
+    unsigned long long c_searched = 0, c_fb = 0, c_probes = 0;
+    const int64_t total = p_a + 1 + p_b + 1;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        bool searched = false, fb = false;
+        int np = 0;
+        int64_t err = 0;
+        if (t <= p_a) {
+            const int64_t xi = BA.start(t);
+            int64_t r = m;
+            if (xi < n) {
+                const K x = A[xi];
+                const int64_t g = predict(model_b, feature(x), m);
+                r = bounded_search<K, false>(B, m, x, g, step0_a, window, np, fb);
+                err = g - r;
+                searched = true;
+            }
+            xbar[t] = r;
+        } else {
+            const int64_t j = t - (p_a + 1);
+            const int64_t yj = BB.start(j);
+            int64_t r = n;
+            if (yj < m) {
+                const K y = B[yj];
+                const int64_t g = predict(model_a, feature(y), n);
+                r = bounded_search<K, true>(A, n, y, g, step0_b, window, np, fb);
+                err = g - r;
+                searched = true;
+            }
+            ybar[j] = r;
         }
-        xbar[t] = r;
-    } else if (t <= p_a + 1 + p_b) {
-        const int64_t j = t - (p_a + 1);
-        const int64_t yj = Blocks<int64_t>(m, p_b).start(j);
-        int64_t r = n;
-        if (yj < m) {
-            const K y = B[yj];
-            const int64_t g = predict(model_a, feature(y), n);
-            r = bounded_search<K, true>(A, n, y, g, step0_b, window, np, fb);
-            err = g - r;
-            searched = true;
+        if (searched) {
+            atomicAdd(&sh[error_bin(err)], 1u);
+            c_searched += 1;
+            c_fb += fb ? 1 : 0;
+            c_probes += (unsigned long long)np;
         }
-        ybar[j] = r;
     }
-    if (searched) {
-        atomicAdd(&sh[error_bin(err)], 1u);
-        atomicAdd(&sc[0], 1ull);
-        if (fb) atomicAdd(&sc[1], 1ull);
-        atomicAdd(&sc[2], (unsigned long long)np);
+    for (int o = 32; o > 0; o >>= 1) {
+        c_searched += __shfl_xor(c_searched, o);
+        c_fb += __shfl_xor(c_fb, o);
+        c_probes += __shfl_xor(c_probes, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c_searched) atomicAdd(&sc[0], c_searched);
+        if (c_fb) atomicAdd(&sc[1], c_fb);
+        if (c_probes) atomicAdd(&sc[2], c_probes);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
@@ -465,8 +502,9 @@ hipError_t launch_learned_partition(int dtype, const void* keys, int64_t n, int6
                                     int64_t step0_a, int64_t step0_b, int64_t window, int64_t* xbar,
                                     int64_t* ybar, uint64_t* hist, uint64_t* counters,
                                     hipStream_t st) {
-    const int64_t threads = p_a + p_b + 2;
-    const unsigned grid = (unsigned)((threads + 255) / 256);
+    // a grid-stride loop over the p_a + 1 + p_b + 1 cross ranks, with
+    // enough workgroups to fill the device several times over
+    const unsigned grid = grid_for(p_a + p_b + 2, (int64_t)device_cu_count() * 16);
     with_key(dtype, [&](auto z) {
         using K = decltype(z);
         learned_partition_kernel<K><<<grid, 256, 0, st>>>(

@@ -369,7 +369,47 @@ def test_gallop_exact(is_high):
                     # probe at g, gallop to at most 2*dist, bisect the bracket
                     assert probes <= 2 + 2 * (dist.bit_length() + 1)
                 if fb:
-                    assert probes >= int(np.floor(np.log2(n + 1)))
+                    # probe g, the steps up to the window, then the whole of
+                    # [0, n] with aligned splits (at most bitlen(n) + 1 reads)
+                    assert probes <= 1 + (W.bit_length() + 1) + n.bit_length() + 1
+
+
+def _trailing_zeros(t: int) -> int:
+    return (t & -t).bit_length() - 1
+
+
+def _aligned_probe_count(lo: int, hi: int, r: int) -> int:
+    """Reads of the aligned bisection of [lo, hi] for the answer r, from its
+    definition: each read splits at the number in (lo, hi] with the most
+    trailing zero bits (found here by scanning the whole interval)."""
+    count = 0
+    while lo < hi:
+        m = max(range(lo + 1, hi + 1), key=_trailing_zeros)
+        count += 1
+        if r >= m:
+            lo = m
+        else:
+            hi = m - 1
+    return count
+
+
+@pytest.mark.parametrize("is_high", [False, True])
+def test_gallop_aligned_bisection(is_high):
+    """With window 0 every search gives up at once: after the probe of g it
+    bisects [0, n] at the points of most trailing zeros.  Its read count
+    equals the count of that definition, and is at most bitlen(n) + 1."""
+    g = np.random.default_rng(14)
+    for _ in range(300):
+        n = int(g.integers(0, 700))
+        X = rand_sorted(g, n, int(g.integers(1, 200)), np.uint32)
+        x = rand_sorted(g, 1, 256, np.uint32)[0]
+        r = int(np.sum(X <= x)) if is_high else int(np.sum(X < x))
+        for e in (0, 3, -5, 10_000):
+            gs = min(max(r + e, 0), n)
+            got, probes, fb = oracle.gallop(x, X, is_high, r + e, 0)
+            assert got == r and fb
+            assert probes == int(gs < n) + _aligned_probe_count(0, n, r)
+            assert probes <= int(gs < n) + n.bit_length() + 1
 
 
 @pytest.mark.parametrize("is_high", [False, True])
