@@ -502,9 +502,12 @@ hipError_t launch_learned_partition(int dtype, const void* keys, int64_t n, int6
                                     int64_t step0_a, int64_t step0_b, int64_t window, int64_t* xbar,
                                     int64_t* ybar, uint64_t* hist, uint64_t* counters,
                                     hipStream_t st) {
-    // a grid-stride loop over the p_a + 1 + p_b + 1 cross ranks, with
-    // enough workgroups to fill the device several times over
-    const unsigned grid = grid_for(p_a + p_b + 2, (int64_t)device_cu_count() * 16);
+    // a grid-stride loop over the p_a + 1 + p_b + 1 cross ranks with 64
+    // workgroups per CU: at 2^25 ranks, 16 or fewer per CU leave the device
+    // short of searches in flight, and one rank per thread (512 per CU)
+    // spends the time on the per-workgroup counter atomics (measured 1.26,
+    // 1.19 and 1.75 ms)
+    const unsigned grid = grid_for(p_a + p_b + 2, (int64_t)device_cu_count() * 64);
     with_key(dtype, [&](auto z) {
         using K = decltype(z);
         learned_partition_kernel<K><<<grid, 256, 0, st>>>(
