@@ -232,26 +232,30 @@ __global__ __launch_bounds__(L) void merge_direct_kernel(
     write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
 }
 
-// Steps 3-4 for partitions into small blocks (a subproblem of at most a few
-// dozen elements): one lane per subproblem picks its case from xbar / ybar
-// and merges straight from global memory with the stable two-pointer rule
-// (B first only when strictly smaller), with no descriptor in between.
+// ---------------------------------------------------------------------------
+// Steps 3-4 for partitions into small blocks (subproblems of at most a few
+// dozen elements), without descriptors.
+//
+// Workgroup g owns the A blocks [i0, i1) (kFineG of them) and every B block
+// whose start y_j lies in [xbar_i0, xbar_i1).  The outputs of these pieces
+// are exactly C[x_i0 + xbar_i0, x_i1 + xbar_i1) (workgroup 0 starts at 0):
+// the elements placed there are A[x_i0, x_i1) and B[xbar_i0, xbar_i1), since
+// A[x_i] lands at x_i + xbar_i.  So the workgroup stages both input ranges
+// with 16-byte loads, merges each piece from LDS into an LDS copy of its
+// output range, and writes that range with 16-byte stores.  A range too
+// large for the staging buffers (many B elements between two A block
+// starts) falls back to merging each piece straight from global memory.
+// ---------------------------------------------------------------------------
+constexpr int kFineG = 64;     // A blocks per workgroup
+constexpr int kFineL = 128;    // threads per workgroup
+
+// One piece merged straight from global memory with the stable two-pointer
+// rule (B first only when strictly smaller).
 template <typename K, bool PAY>
-__global__ __launch_bounds__(256) void fine_merge_kernel(const K* __restrict__ keys,
-                                                         const uint32_t* __restrict__ pay, int64_t n,
-                                                         int64_t m, int64_t p_a, int64_t p_b,
-                                                         const int64_t* __restrict__ xbar,
-                                                         const int64_t* __restrict__ ybar,
-                                                         K* __restrict__ out,
-                                                         uint32_t* __restrict__ out_pay) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= p_a + p_b) return;
-    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
-    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
-                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
-    if (!(0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= n && 0 <= pc.b_lo &&
-          pc.b_lo <= pc.b_hi && pc.b_hi <= m))
-        return;  // cannot happen for cross ranks of sorted inputs; never write outside C
+__device__ __forceinline__ void fine_piece_global(const K* __restrict__ keys,
+                                                  const uint32_t* __restrict__ pay, int64_t n,
+                                                  const Piece<int64_t>& pc, K* __restrict__ out,
+                                                  uint32_t* __restrict__ out_pay) {
     const K* A = keys;
     const K* B = keys + n;
     int64_t ia = pc.a_lo, ib = pc.b_lo, o = pc.a_lo + pc.b_lo;
@@ -274,43 +278,147 @@ __global__ __launch_bounds__(256) void fine_merge_kernel(const K* __restrict__ k
     }
 }
 
-// Keys-only form for parts of at most NB elements each: the lane loads its
-// A part and its B part into registers (positions past a part hold the key
-// type's maximum), merges the 2 NB keys with a merging network, and stores
-// the first la + lb.  Without payloads equal keys are indistinguishable, so
-// the network's order among ties does not matter.  All loads of a lane are
-// independent, so they are in flight together.
-template <typename K, int NB>
-__global__ __launch_bounds__(256) void fine_merge_net_kernel(const K* __restrict__ keys, int64_t n,
-                                                             int64_t m, int64_t p_a, int64_t p_b,
-                                                             const int64_t* __restrict__ xbar,
-                                                             const int64_t* __restrict__ ybar,
-                                                             K* __restrict__ out) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= p_a + p_b) return;
-    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
-    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
-                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
-    const int64_t la = pc.a_hi - pc.a_lo, lb = pc.b_hi - pc.b_lo;
-    if (!(0 <= pc.a_lo && la >= 0 && pc.a_hi <= n && 0 <= pc.b_lo && lb >= 0 && pc.b_hi <= m &&
-          la <= NB && lb <= NB))
-        return;  // cannot happen for cross ranks of sorted inputs; never write outside C
-    const int64_t last = n + m - 1;
-    K v[2 * NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int64_t ia = pc.a_lo + i < last ? pc.a_lo + i : last;
-        const int64_t ib = n + pc.b_lo + i < last ? n + pc.b_lo + i : last;
-        const K ka = keys[ia], kb = keys[ib];
-        v[i] = i < la ? ka : KeyMax<K>::v;
-        v[NB + i] = i < lb ? kb : KeyMax<K>::v;
+// LDS of the staged small-block merge: A window, B window, output window
+// (keys; payloads alike), each with a 16-byte alignment margin.
+struct FineSmem {
+    int ka, kb, kc;   // slots per window
+    __host__ __device__ FineSmem(int capA, int capB) {
+        ka = (capA + 16 + 7) & ~7;
+        kb = (capB + 16 + 7) & ~7;
+        kc = (capA + capB + 16 + 7) & ~7;
     }
-    OddEvenMerge<0, 2 * NB - 1, 1>::template run<K>(v);
-    K* o = out + pc.a_lo + pc.b_lo;
-    const int len = (int)(la + lb);
+    // esz = bytes per element: key size, plus 4 with payloads
+    __host__ __device__ uint32_t bytes_for(int esz) const {
+        return (uint32_t)(ka + kb + kc) * (uint32_t)esz;
+    }
+};
+
+// 16-byte chunks of src[lo, lo + len) (src 16-byte aligned at index 0) into
+// dst: element lo + k lands at dst[off + k], off = lo % V.
+template <typename E, int L>
+__device__ __forceinline__ int stage_range(const E* src, uint64_t src_len, int64_t lo, int len,
+                                           E* dst) {
+    constexpr int V = 16 / sizeof(E);
+    const int off = (int)(lo % V);
+    const int64_t al = lo - off;
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(src + al, (src_len - (uint64_t)al) * sizeof(E));
+    const int nch = (off + len + V - 1) / V;
+    for (int q = threadIdx.x; q < nch; q += L)
+        *reinterpret_cast<u32x4*>(dst + q * V) = buf_load16(r, (uint32_t)q * 16u);
+    return off;
+}
+
+template <typename K, bool PAY>
+__global__ __launch_bounds__(kFineL) void fine_merge_staged_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t n, int64_t m,
+    int64_t p_a, int64_t p_b, const int64_t* __restrict__ xbar, const int64_t* __restrict__ ybar,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int capA, int capB) {
+    constexpr int L = kFineL;
+    extern __shared__ __align__(16) char smem[];
+    const FineSmem fs(capA, capB);
+    K* sA = reinterpret_cast<K*>(smem);
+    K* sB = sA + fs.ka;
+    K* sC = sB + fs.kb;
+    uint32_t* qA = reinterpret_cast<uint32_t*>(sC + fs.kc);
+    uint32_t* qB = qA + fs.ka;
+    uint32_t* qC = qB + fs.kb;
+
+    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
+    const int64_t i0 = (int64_t)blockIdx.x * kFineG;
+    if (i0 >= p_a) return;
+    const int64_t i1 = i0 + kFineG < p_a ? i0 + kFineG : p_a;
+    const int64_t a_lo = BA.start(i0), a_hi = BA.start(i1);
+    const int64_t b_lo = blockIdx.x == 0 ? 0 : xbar[i0];
+    const int64_t b_hi = xbar[i1];
+    const int64_t c_lo = a_lo + b_lo;
+    // B blocks whose start lies in [b_lo, b_hi)
+    auto first_start_at_or_after = [&](int64_t pos) {
+        int64_t j = BB.of(pos);
+        if (j < p_b && BB.start(j) < pos) ++j;
+        return j;
+    };
+    const int64_t j0 = first_start_at_or_after(b_lo), j1 = first_start_at_or_after(b_hi);
+    const int64_t na = a_hi - a_lo, nb = b_hi - b_lo;
+    const int64_t npa = i1 - i0, npieces = npa + (j1 - j0);
+    if (!(0 <= b_lo && b_lo <= b_hi && b_hi <= m && j0 <= j1)) return;  // cannot happen
+
+    auto piece = [&](int64_t idx) {
+        return idx < npa ? step3_piece<int64_t>(BA, BB, xbar, ybar, i0 + idx)
+                         : step4_piece<int64_t>(BA, BB, xbar, ybar, j0 + (idx - npa));
+    };
+    auto inside = [&](const Piece<int64_t>& pc) {
+        return a_lo <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= a_hi && b_lo <= pc.b_lo &&
+               pc.b_lo <= pc.b_hi && pc.b_hi <= b_hi;
+    };
+
+    if (na > capA || nb > capB) {
+        // too many elements to stage: each piece from global memory
+        for (int64_t idx = threadIdx.x; idx < npieces; idx += L) {
+            const Piece<int64_t> pc = piece(idx);
+            if (inside(pc)) fine_piece_global<K, PAY>(keys, pay, n, pc, out, out_pay);
+        }
+        return;
+    }
+
+    const uint64_t total = (uint64_t)(n + m);
+    const int offA = stage_range<K, L>(keys, total, a_lo, (int)na, sA);
+    const int offB = stage_range<K, L>(keys, total, n + b_lo, (int)nb, sB);
+    if (PAY) {
+        stage_range<uint32_t, L>(pay, total, a_lo, (int)na, qA);
+        stage_range<uint32_t, L>(pay, total, n + b_lo, (int)nb, qB);
+    }
+    constexpr int V = 16 / sizeof(K);
+    const int offC = (int)(c_lo % V);
+    const int offCP = (int)(c_lo % 4);
+    const int offPA = (int)(a_lo % 4), offPB = (int)((n + b_lo) % 4);
+    __syncthreads();
+
+    for (int64_t idx = threadIdx.x; idx < npieces; idx += L) {
+        const Piece<int64_t> pc = piece(idx);
+        if (!inside(pc)) continue;  // cannot happen for cross ranks of sorted inputs
+        const int la = (int)(pc.a_hi - pc.a_lo), lb = (int)(pc.b_hi - pc.b_lo);
+        const int ia = offA + (int)(pc.a_lo - a_lo), ib = offB + (int)(pc.b_lo - b_lo);
+        const int oc = (int)(pc.c_off - c_lo);
+        if (!PAY && la <= 16 && lb <= 16) {
+            // both parts into registers (past a part: the key type's maximum),
+            // Batcher's odd-even merge, the first la + lb back to LDS; without
+            // payloads the order among equal keys is not observable
+            K v[32];
 #pragma unroll
-    for (int k = 0; k < 2 * NB; ++k)
-        if (k < len) o[k] = v[k];
+            for (int i = 0; i < 16; ++i) {
+                v[i] = i < la ? sA[ia + i] : KeyMax<K>::v;
+                v[16 + i] = i < lb ? sB[ib + i] : KeyMax<K>::v;
+            }
+            OddEvenMerge<0, 31, 1>::template run<K>(v);
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (k < la + lb) sC[offC + oc + k] = v[k];
+        } else {
+            // stable two-pointer merge in LDS
+            const int pa0 = offPA + (int)(pc.a_lo - a_lo), pb0 = offPB + (int)(pc.b_lo - b_lo);
+            int x = 0, y = 0, k = offC + oc, kp = offCP + oc;
+            while (x < la && y < lb) {
+                const K ka = sA[ia + x], kb = sB[ib + y];
+                const bool tb = kb < ka;
+                sC[k++] = tb ? kb : ka;
+                if (PAY) qC[kp++] = tb ? qB[pb0 + y] : qA[pa0 + x];
+                y += tb;
+                x += !tb;
+            }
+            for (; x < la; ++x) {
+                sC[k++] = sA[ia + x];
+                if (PAY) qC[kp++] = qA[pa0 + x];
+            }
+            for (; y < lb; ++y) {
+                sC[k++] = sB[ib + y];
+                if (PAY) qC[kp++] = qB[pb0 + y];
+            }
+        }
+    }
+    __syncthreads();
+    const int s = (int)(na + nb);
+    write_out<K, L, 0>(sC, offC, s, out + (c_lo - offC));
+    if (PAY) write_out<uint32_t, L, 0>(qC, offCP, s, out_pay + (c_lo - offCP));
 }
 
 template <typename K>
@@ -521,28 +629,44 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
                             int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                             const int64_t* ybar, void* out_keys, uint32_t* out_pay,
                             hipStream_t st) {
-    const int64_t P = p_a + p_b;
-    if (P <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((P + 255) / 256);
-    // parts are bounded by the block lengths
-    const int64_t la_max = p_a > 0 ? (n + p_a - 1) / p_a : 0;
-    const int64_t lb_max = p_b > 0 ? (m + p_b - 1) / p_b : 0;
-    const bool net = !pay && n + m > 0 && la_max <= 16 && lb_max <= 16;
+    if (p_a + p_b <= 0 || n + m <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((p_a + kFineG - 1) / kFineG);
+    // staging capacity: the workgroup's A blocks in full, and twice that (at
+    // least 2048) of B, within 64 KiB of LDS (B shrinks first; if A alone
+    // does not fit, nothing is staged); a workgroup whose ranges exceed the
+    // capacity merges from global memory
+    const int64_t la_max = (n + p_a - 1) / p_a;
+    const int ksz = dtype == 2 ? 8 : 4;
+    const int esz = ksz + (pay ? 4 : 0);
+    int capA = (int)(kFineG * (la_max > 0 ? la_max : 1));
+    int capB = 2 * capA > 2048 ? 2 * capA : 2048;
+    constexpr uint32_t kFineLds = 64 * 1024;
+    while (capB > capA && FineSmem(capA, capB).bytes_for(esz) > kFineLds) capB /= 2;
+    if (FineSmem(capA, capB).bytes_for(esz) > kFineLds) capA = capB = 0;
+    const FineSmem fs(capA, capB);
+    hipError_t e = hipSuccess;
     with_dtype(dtype, [&](auto z) {
         using K = decltype(z);
-        if (net)
-            fine_merge_net_kernel<K, 16><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), n, m, p_a,
-                                                               p_b, xbar, ybar,
-                                                               static_cast<K*>(out_keys));
-        else if (pay)
-            fine_merge_kernel<K, true><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), pay, n, m,
-                                                             p_a, p_b, xbar, ybar,
-                                                             static_cast<K*>(out_keys), out_pay);
-        else
-            fine_merge_kernel<K, false><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), nullptr,
-                                                              n, m, p_a, p_b, xbar, ybar,
-                                                              static_cast<K*>(out_keys), nullptr);
+        const uint32_t lds = fs.bytes_for(esz);
+        if (pay) {
+            auto kern = fine_merge_staged_kernel<K, true>;
+            static bool attr = false;
+            if (!attr && (e = allow_big_lds(kern)) == hipSuccess) attr = true;
+            if (e == hipSuccess)
+                kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), pay, n, m, p_a, p_b,
+                                                xbar, ybar, static_cast<K*>(out_keys), out_pay,
+                                                capA, capB);
+        } else {
+            auto kern = fine_merge_staged_kernel<K, false>;
+            static bool attr = false;
+            if (!attr && (e = allow_big_lds(kern)) == hipSuccess) attr = true;
+            if (e == hipSuccess)
+                kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), nullptr, n, m, p_a,
+                                                p_b, xbar, ybar, static_cast<K*>(out_keys),
+                                                nullptr, capA, capB);
+        }
     });
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

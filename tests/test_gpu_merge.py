@@ -178,6 +178,27 @@ def test_small_blocks_keys_only(dtype):
             check(A, B, False, **kw)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_small_blocks_staging_limits(dtype, with_pay):
+    """Small blocks where one workgroup's 64 A blocks enclose far more B
+    elements than it stages (it merges from global memory), mixed with
+    workgroups that stage; empty sides; blocks of one element."""
+    g = np.random.default_rng(9)
+    for n, m, alpha, kw in [(100, 100_000, 1 << 20, dict(tile=1)),
+                            (100_000, 100, 1 << 20, dict(tile=1)),
+                            (5000, 300_000, 1 << 16, dict(p_a=5000 // 16, p_b=300_000 // 16)),
+                            (0, 5000, 100, dict(tile=1)), (5000, 0, 100, dict(tile=1)),
+                            (70_001, 70_003, 3, dict(tile=16)),
+                            (1 << 16, 1 << 16, 1 << 30, dict(tile=32))]:
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        # clustered keys: many B elements between neighbouring A block starts
+        if n and m and alpha == 1 << 16:
+            B = np.sort(np.concatenate([B[: m // 2], np.full(m - m // 2, A[n // 2], dtype)]))
+        flush(f"staging limits dtype={np.dtype(dtype).name} pay={with_pay} n={n} m={m} {kw}")
+        check(A, B, with_pay, **kw)
+
+
 def test_validate_detects_unsorted():
     A = np.array([1, 2, 3, 2], dtype=np.uint32)
     B = np.array([1, 5], dtype=np.uint32)
