@@ -464,13 +464,15 @@ hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m, i
 }
 
 int device_cu_count() {
-    static int cus = 0;
+    static std::atomic<int> cached{0};
+    int cus = cached.load(std::memory_order_relaxed);
     if (cus == 0) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
+        cached.store(cus, std::memory_order_relaxed);
     }
     return cus;
 }
@@ -479,6 +481,17 @@ template <typename Kern>
 static hipError_t allow_big_lds(Kern kern) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+}
+
+// allow_big_lds once per kernel: `done` is that kernel's own flag (setting
+// the attribute twice, from two threads racing on the first call, is
+// harmless)
+template <typename Kern>
+static hipError_t allow_big_lds_once(Kern kern, std::atomic<bool>& done) {
+    if (done.load(std::memory_order_acquire)) return hipSuccess;
+    const hipError_t e = allow_big_lds(kern);
+    if (e == hipSuccess) done.store(true, std::memory_order_release);
+    return e;
 }
 
 // Workgroups of a persistent merge kernel that fit one compute unit at once.
@@ -531,12 +544,10 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
     const bool whole = (uint64_t)nkeys * sizeof(K) < (1ull << 32) - 4096;
     if constexpr (R <= 5) {
         if (whole) {
-            auto go = [&](auto kern, bool& attr2, std::atomic<uint64_t>& occ) -> hipError_t {
-                if (!attr2) {
-                    hipError_t e = allow_big_lds(kern);
-                    if (e != hipSuccess) return e;
-                    attr2 = true;
-                }
+            auto go = [&](auto kern, std::atomic<bool>& attr2,
+                          std::atomic<uint64_t>& occ) -> hipError_t {
+                const hipError_t e = allow_big_lds_once(kern, attr2);
+                if (e != hipSuccess) return e;
                 const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
                 int64_t grid = (int64_t)device_cu_count() * resident_per_cu(kern, lds, occ);
                 if (grid > P) grid = P;
@@ -544,7 +555,7 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
                                                      P_dev, cap);
                 return hipGetLastError();
             };
-            static bool attr2 = false;
+            static std::atomic<bool> attr2{false};
             static std::atomic<uint64_t> occ2{0};
             if constexpr (sizeof(K) == 8 && PAY)
                 return go(merge_pipelined_wide_kernel<K, PAY, L, R>, attr2, occ2);
@@ -553,11 +564,10 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
         }
     }
     auto kern = merge_persistent_kernel<K, PAY, L, R>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = allow_big_lds(kern);
+    static std::atomic<bool> attr{false};
+    {
+        const hipError_t e = allow_big_lds_once(kern, attr);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
     static std::atomic<uint64_t> occ{0};
@@ -590,11 +600,10 @@ static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_
                                             st);
     constexpr int L = kMergeThreads;
     auto kern = merge_direct_kernel<K, PAY, L>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = allow_big_lds(kern);
+    static std::atomic<bool> attr{false};
+    {
+        const hipError_t e = allow_big_lds_once(kern, attr);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
     kern<<<(unsigned)P, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
@@ -650,16 +659,16 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
         const uint32_t lds = fs.bytes_for(esz);
         if (pay) {
             auto kern = fine_merge_staged_kernel<K, true>;
-            static bool attr = false;
-            if (!attr && (e = allow_big_lds(kern)) == hipSuccess) attr = true;
+            static std::atomic<bool> attr{false};
+            e = allow_big_lds_once(kern, attr);
             if (e == hipSuccess)
                 kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), pay, n, m, p_a, p_b,
                                                 xbar, ybar, static_cast<K*>(out_keys), out_pay,
                                                 capA, capB);
         } else {
             auto kern = fine_merge_staged_kernel<K, false>;
-            static bool attr = false;
-            if (!attr && (e = allow_big_lds(kern)) == hipSuccess) attr = true;
+            static std::atomic<bool> attr{false};
+            e = allow_big_lds_once(kern, attr);
             if (e == hipSuccess)
                 kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), nullptr, n, m, p_a,
                                                 p_b, xbar, ybar, static_cast<K*>(out_keys),
