@@ -22,7 +22,11 @@ namespace sm {
 
 namespace {
 
-constexpr int kRunThreads = 256;
+// threads sorting one run: two elements each, at most 1024 (the rank
+// searches are chains of dependent LDS reads, so the more waves share a CU
+// the better their latency is hidden)
+template <int RUN>
+constexpr int run_threads() { return RUN / 2 < 1024 ? RUN / 2 : 1024; }
 
 template <typename K, bool PAY, int RUN>
 struct RunSmem {
@@ -37,10 +41,10 @@ struct RunSmem {
 template <typename K, bool PAY, int RUN>
 // keys / out (and pay / out_pay) may be the same array: a workgroup reads
 // its whole run before it writes any of it.
-__global__ __launch_bounds__(kRunThreads) void sort_runs_kernel(const K* keys, const uint32_t* pay,
+__global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(const K* keys, const uint32_t* pay,
                                                                 int64_t N, K* out,
                                                                 uint32_t* out_pay) {
-    constexpr int T = kRunThreads;
+    constexpr int T = run_threads<RUN>();
     constexpr int E = RUN / T;
     static_assert(RUN % T == 0 && (RUN & (RUN - 1)) == 0, "RUN: power of two, multiple of T");
     __shared__ RunSmem<K, PAY, RUN> s;
@@ -122,14 +126,14 @@ hipError_t launch_runs_t(const K* keys, const uint32_t* pay, int64_t N, K* out, 
                          int run, hipStream_t st) {
     const int64_t g = (N + run - 1) / run;
     switch (run) {
-        case 256: sort_runs_kernel<K, PAY, 256><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
-        case 512: sort_runs_kernel<K, PAY, 512><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
-        case 1024: sort_runs_kernel<K, PAY, 1024><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
-        case 2048: sort_runs_kernel<K, PAY, 2048><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay); break;
+        case 256: sort_runs_kernel<K, PAY, 256><<<(unsigned)g, run_threads<256>(), 0, st>>>(keys, pay, N, out, out_pay); break;
+        case 512: sort_runs_kernel<K, PAY, 512><<<(unsigned)g, run_threads<512>(), 0, st>>>(keys, pay, N, out, out_pay); break;
+        case 1024: sort_runs_kernel<K, PAY, 1024><<<(unsigned)g, run_threads<1024>(), 0, st>>>(keys, pay, N, out, out_pay); break;
+        case 2048: sort_runs_kernel<K, PAY, 2048><<<(unsigned)g, run_threads<2048>(), 0, st>>>(keys, pay, N, out, out_pay); break;
         case 4096:
             // 32-bit keys only: two buffers of 4096 keys and payloads fill 64 KiB
             if constexpr (sizeof(K) == 4) {
-                sort_runs_kernel<K, PAY, 4096><<<(unsigned)g, kRunThreads, 0, st>>>(keys, pay, N, out, out_pay);
+                sort_runs_kernel<K, PAY, 4096><<<(unsigned)g, run_threads<4096>(), 0, st>>>(keys, pay, N, out, out_pay);
                 break;
             } else {
                 return hipErrorInvalidValue;
