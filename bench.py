@@ -123,8 +123,9 @@ def main():
     ap.add_argument("--check", action="store_true", help="compare one output with the oracle")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, sort and learned measurements")
-    ap.add_argument("--extras", default="batched,batched_literal,sort,learned",
-                    help="comma-separated subset of batched, batched_literal, sort, learned")
+    ap.add_argument("--extras", default="heavy_ties,skewed,batched,batched_literal,sort,learned",
+                    help="comma-separated subset of heavy_ties, skewed, batched, "
+                         "batched_literal, sort, learned")
     ap.add_argument("--sort-run", type=int, default=512, help="run length of the merge sort")
     ap.add_argument("--batch-log2max", type=int, default=15,
                     help="batched pairs: totals log-uniform in [16, 2^this]")
@@ -259,6 +260,14 @@ def main():
         del keys, out, ws, xbar, ybar, A, B
         torch.cuda.empty_cache()
         extras = set(args.extras.split(","))
+        if "heavy_ties" in extras:
+            res["heavy_ties"] = bench_heavy_ties(args)
+            log(f"bench: heavy_ties {json.dumps(res['heavy_ties'])}")
+            torch.cuda.empty_cache()
+        if "skewed" in extras:
+            res["skewed"] = bench_skewed(args)
+            log(f"bench: skewed {json.dumps(res['skewed'])}")
+            torch.cuda.empty_cache()
         if "batched" in extras:
             res["batched"] = bench_batched(args, gelems, args.batch_log2max)
             log(f"bench: batched {json.dumps(res['batched'])}")
@@ -393,6 +402,114 @@ def bench_batched(args, plain_gelems, log2max):
             "per_pair_calls": {"pairs_sampled": len(sample), "Gelem/s": round(pp_gel, 3),
                                "speedup_of_batched": round(gel / pp_gel, 1)},
             "vs_plain_merge_Gelem/s": round(gel / plain_gelems, 3)}
+
+
+def bench_heavy_ties(args):
+    """A = 1,000,000 and B = 600,000 int32 keys uniform in [0, 65536) (about
+    15 and 9 copies of every value), payload = source tag << 31 | index,
+    p_a = p_b = 256 forced: the whole stable_merge call's latency.  The
+    inputs (25.6 MB in and out) stay in the last-level cache, so latency,
+    not HBM bandwidth, is the figure."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_1202_6575_amd as sm
+
+    n, m = 1_000_000, 600_000
+    log("bench: heavy ties, n=1e6, m=6e5 int32, p=256")
+    A, B = datagen.uniform_pair(n, m, 0, 65536, np.int32, seed=datagen.BASE_SEED + 0)
+    pa, pb = datagen.source_tag_payloads(n, m)
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(np.concatenate([A, B])).to(dev)
+    pay = torch.from_numpy(np.concatenate([pa, pb])).to(dev)
+    ok, op = torch.empty_like(keys), torch.empty_like(pay)
+    ws = torch.empty(sm.workspace_bytes(n, m, torch.int32, True, p_a=256, p_b=256),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        sm.merge(keys, n, m, pay, out_keys=ok, out_payloads=op, p_a=256, p_b=256,
+                 workspace=ws, stream=stream)
+
+    for _ in range(3):
+        run()
+    times = []
+    for _ in range(max(args.steps, 20)):
+        times.append(_events_ms(run, 1, stream))
+    med = float(np.median(times))
+    return {"workload": "A 1e6 and B 6e5 int32 uniform in [0, 65536), payload src<<31|index, "
+                        "p_a = p_b = 256",
+            "latency_us_median": round(med * 1e3, 1),
+            "latency_us_min": round(min(times) * 1e3, 1),
+            "Gelem/s": round((n + m) / (med * 1e-3) / 1e9, 2)}
+
+
+def bench_skewed(args):
+    """A = 2^27 and B = 2^23 uint64 keys, Zipf(1.1) over 10^6 distinct
+    values, uint32 payload = index in A ‖ B: Gelem/s, the partition / merge
+    split, the merge kernel's HBM roofline, and the sizes of the p_a + p_b
+    subproblems (load balance under massive ties and m << n)."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_1202_6575_amd as sm
+
+    n, m = 1 << 27, 1 << 23
+    log("bench: skewed, n=2^27, m=2^23 uint64 Zipf(1.1) with payloads")
+    A, B = datagen.zipf_pair(n, m, 1.1, 10 ** 6, seed=datagen.BASE_SEED + 2)
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(np.concatenate([A, B]).view(np.int64)).to(dev).view(torch.uint64)
+    del A, B
+    pay = torch.arange(n + m, dtype=torch.int64, device=dev).to(torch.int32).view(torch.uint32)
+    ok, op = torch.empty_like(keys), torch.empty_like(pay)
+    tile = 1024                          # the library's default block length for uint64 + payload
+    p_a, p_b = (n + tile - 1) // tile, (m + tile - 1) // tile
+    xbar = torch.empty(p_a + 1, dtype=torch.int64, device=dev)
+    ybar = torch.empty(p_b + 1, dtype=torch.int64, device=dev)
+    ws = torch.empty(sm.pieces_workspace_bytes(n, m, p_a, p_b, torch.uint64, True),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def part():
+        sm.partition(keys, n, m, p_a, p_b, xbar=xbar, ybar=ybar, stream=stream)
+
+    def pieces():
+        sm.merge_pieces(keys, n, m, p_a, p_b, xbar, ybar, pay, out_keys=ok, out_payloads=op,
+                        workspace=ws, stream=stream)
+
+    part()
+    pieces()
+    torch.cuda.synchronize()
+    steps = max(args.steps, 5)
+    part_ms = _events_ms(part, steps, stream)
+    merge_ms = _events_ms(pieces, steps, stream)
+    alg = (n + m) * (8 + 4) * 2
+    # subproblem sizes: the 2p pieces tile C in the order of their output
+    # offsets x_i + xbar_i and y_j + ybar_j
+    def starts(length, p):
+        i = torch.arange(p, dtype=torch.int64, device=dev)
+        q, r = length // p, length % p
+        return i * q + torch.minimum(i, torch.tensor(r, device=dev))
+    c = torch.cat([starts(n, p_a) + xbar[:p_a], starts(m, p_b) + ybar[:p_b],
+                   torch.tensor([n + m], dtype=torch.int64, device=dev)])
+    sizes = torch.diff(torch.sort(c).values)
+    hist = torch.bincount(torch.floor(torch.log2(sizes.double() + 1)).long()).cpu().tolist()
+    sz = sizes.double()
+    return {"workload": "A 2^27 and B 2^23 uint64, Zipf(1.1) over 10^6 distinct values, "
+                        "uint32 payload = index in A||B",
+            "tile": tile, "p_a": p_a, "p_b": p_b,
+            "Gelem/s": round((n + m) / ((part_ms + merge_ms) * 1e-3) / 1e9, 2),
+            "phases_ms": {"partition (Steps 1-2)": round(part_ms, 4),
+                          "cases + merge (Steps 3-4)": round(merge_ms, 4)},
+            "roofline": {"bound": "hbm", "achieved": round(alg / (merge_ms * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(alg / (merge_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_launch": alg},
+            "subproblem_sizes": {"count": int(sizes.numel()), "mean": round(float(sz.mean()), 1),
+                                 "max": int(sizes.max()), "bound_2_blocks": 2 * tile,
+                                 "p99": int(torch.quantile(sz, 0.99)),
+                                 "log2_histogram": {f"[{(1 << k) - 1},{(1 << (k + 1)) - 1})": v
+                                                    for k, v in enumerate(hist) if v}}}
 
 
 def bench_sort(args):
