@@ -16,8 +16,11 @@
  *    caller.  The library never allocates, frees or retains caller memory.
  *  - Keys of A and B are stored contiguously in one buffer: A = keys[0, n),
  *    B = keys[n, n + m).  Payloads (optional, uint32) use the same layout.
- *  - Key type (dtype): SM_INT32 compares as signed 32-bit, SM_UINT32 and
- *    SM_UINT64 compare as unsigned.  Key, payload and output arrays passed to
+ *  - Key type (dtype): SM_INT32 and SM_INT64 compare as signed integers,
+ *    SM_UINT32 and SM_UINT64 as unsigned; SM_FLOAT32 and SM_FLOAT64 follow
+ *    IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN,
+ *    NaNs ordered by payload), so every bit pattern is a key and -0 comes
+ *    strictly before +0.  Key, payload and output arrays passed to
  *    the merge entry points must start on a 16-byte boundary (the kernels
  *    move 16-byte chunks); the partition entry point needs element
  *    alignment only.
@@ -47,7 +50,10 @@ extern "C" {
 typedef enum {
     SM_INT32 = 0,
     SM_UINT32 = 1,
-    SM_UINT64 = 2
+    SM_UINT64 = 2,
+    SM_INT64 = 3,
+    SM_FLOAT32 = 4,
+    SM_FLOAT64 = 5
 } sm_dtype;
 
 typedef enum {
@@ -206,8 +212,9 @@ SM_API size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_pa
  * the ranks, and so every merge, stay exactly those of the paper.
  *
  * The network models the cumulative distribution of a sorted array X:
- * phi(key) = log2(u + 1) / bits (u the key in unsigned order: int32 with its
- * sign bit flipped; bits = 32, or 64 for SM_UINT64), h = ReLU(W1 phi + b1)
+ * phi(key) = log2(u + 1) / bits (u the key's position in its order as an
+ * unsigned integer: signed keys with the sign bit flipped, float keys mapped
+ * through totalOrder; bits = the key width), h = ReLU(W1 phi + b1)
  * with 32 hidden units, y = w2 . h + b2 ~ rank / len(X).  Parameters are 97
  * device floats: W1[0:32], b1[32:64], w2[64:96], b2[96].  All arithmetic is
  * FP32.  A prediction is clamp(rint(y * len), 0, len).

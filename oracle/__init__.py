@@ -24,8 +24,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-INT32, UINT32, UINT64 = 0, 1, 2
-NP_DTYPE = {INT32: np.int32, UINT32: np.uint32, UINT64: np.uint64}
+INT32, UINT32, UINT64, INT64, FLOAT32, FLOAT64 = 0, 1, 2, 3, 4, 5
+NP_DTYPE = {INT32: np.int32, UINT32: np.uint32, UINT64: np.uint64, INT64: np.int64,
+            FLOAT32: np.float32, FLOAT64: np.float64}
 
 
 def build_oracle(force: bool = True) -> str:
@@ -84,6 +85,12 @@ def dtype_code(arr: np.ndarray) -> int:
         return UINT32
     if arr.dtype == np.uint64:
         return UINT64
+    if arr.dtype == np.int64:
+        return INT64
+    if arr.dtype == np.float32:
+        return FLOAT32
+    if arr.dtype == np.float64:
+        return FLOAT64
     raise TypeError(f"unsupported key dtype {arr.dtype}")
 
 

@@ -24,14 +24,26 @@ NPARAM = 3 * HIDDEN + 1
 
 
 def unsigned_order(keys: np.ndarray) -> np.ndarray:
-    """Map keys to unsigned integers with the same order (int32: flip the sign bit)."""
+    """Map keys to unsigned integers with the same order: signed integers with
+    the sign bit flipped; floats by IEEE 754 totalOrder from sign and
+    magnitude (negative: 2^(b-1) - 1 - magnitude, positive: 2^(b-1) +
+    magnitude), returned as Python-exact uint64."""
     if keys.dtype == np.int32:
         return (keys.view(np.uint32) ^ np.uint32(0x80000000)).astype(np.uint64)
+    if keys.dtype == np.int64:
+        return keys.view(np.uint64) ^ np.uint64(1 << 63)
+    if keys.dtype in (np.float32, np.float64):
+        bits = 32 if keys.dtype == np.float32 else 64
+        b = keys.view(np.uint32 if bits == 32 else np.uint64).astype(np.uint64)
+        half = np.uint64(1 << (bits - 1))
+        mag = b & (half - np.uint64(1))
+        neg = (b & half) != 0
+        return np.where(neg, (half - np.uint64(1)) - mag, half + mag)
     return keys.astype(np.uint64)
 
 
 def key_bits(keys: np.ndarray) -> int:
-    return 64 if keys.dtype == np.uint64 else 32
+    return 64 if keys.dtype in (np.uint64, np.int64, np.float64) else 32
 
 
 def features(keys: np.ndarray) -> np.ndarray:

@@ -23,13 +23,34 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_INT32 = 0, ORC_UINT32 = 1, ORC_UINT64 = 2 };
+enum { ORC_INT32 = 0, ORC_UINT32 = 1, ORC_UINT64 = 2, ORC_INT64 = 3, ORC_FLOAT32 = 4,
+       ORC_FLOAT64 = 5 };
 
 /* ------------------------------------------------------------------ */
 /* Element access                                                      */
 /* ------------------------------------------------------------------ */
 
-static size_t key_size(int dtype) { return dtype == ORC_UINT64 ? 8 : 4; }
+static size_t key_size(int dtype)
+{
+    return dtype == ORC_UINT64 || dtype == ORC_INT64 || dtype == ORC_FLOAT64 ? 8 : 4;
+}
+
+/*
+ * IEEE 754 totalOrder of two binary32 / binary64 values given as bit
+ * patterns of `bits` bits: a negative sign orders before a positive one
+ * (so -0 < +0 and -NaN < -inf); with equal signs, the magnitude (exponent
+ * and significand read together as one unsigned number, which orders
+ * numbers, infinities and NaN payloads as totalOrder does) decides,
+ * ascending for positive values and descending for negative ones.
+ */
+static int total_order_lt(uint64_t a, uint64_t b, int bits)
+{
+    const uint64_t sign = (uint64_t)1 << (bits - 1);
+    const uint64_t mag = sign - 1;
+    const int na = (a & sign) != 0, nb = (b & sign) != 0;
+    if (na != nb) return na;
+    return na ? (a & mag) > (b & mag) : (a & mag) < (b & mag);
+}
 
 /* X[i] < Y[j] under the order of the key type. */
 static int key_lt(const void *X, int64_t i, const void *Y, int64_t j, int dtype)
@@ -37,6 +58,11 @@ static int key_lt(const void *X, int64_t i, const void *Y, int64_t j, int dtype)
     switch (dtype) {
     case ORC_INT32:  return ((const int32_t *)X)[i]  < ((const int32_t *)Y)[j];
     case ORC_UINT32: return ((const uint32_t *)X)[i] < ((const uint32_t *)Y)[j];
+    case ORC_INT64:  return ((const int64_t *)X)[i]  < ((const int64_t *)Y)[j];
+    case ORC_FLOAT32:
+        return total_order_lt(((const uint32_t *)X)[i], ((const uint32_t *)Y)[j], 32);
+    case ORC_FLOAT64:
+        return total_order_lt(((const uint64_t *)X)[i], ((const uint64_t *)Y)[j], 64);
     default:         return ((const uint64_t *)X)[i] < ((const uint64_t *)Y)[j];
     }
 }

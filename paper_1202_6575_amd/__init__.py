@@ -10,7 +10,9 @@ library's HIP kernels; there is no fallback path.  If the library is not
 built, importing this package raises.
 
 Keys layout: A = keys[0:n], B = keys[n:n+m] in one contiguous buffer.
-Supported key dtypes: torch.int32 (signed order), torch.uint32, torch.uint64.
+Supported key dtypes: torch.int32 and torch.int64 (signed order), torch.uint32,
+torch.uint64, torch.float32 and torch.float64 (IEEE 754 totalOrder: -NaN < -inf
+< ... < -0 < +0 < ... < +inf < +NaN).
 Payloads: optional torch.uint32 tensor with the same layout.
 """
 from __future__ import annotations
@@ -31,8 +33,9 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-SM_INT32, SM_UINT32, SM_UINT64 = 0, 1, 2
-DTYPES = {torch.int32: SM_INT32, torch.uint32: SM_UINT32, torch.uint64: SM_UINT64}
+SM_INT32, SM_UINT32, SM_UINT64, SM_INT64, SM_FLOAT32, SM_FLOAT64 = 0, 1, 2, 3, 4, 5
+DTYPES = {torch.int32: SM_INT32, torch.uint32: SM_UINT32, torch.uint64: SM_UINT64,
+          torch.int64: SM_INT64, torch.float32: SM_FLOAT32, torch.float64: SM_FLOAT64}
 STATUS = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_DTYPE", -3: "SM_ERR_ALIAS",
           -4: "SM_ERR_WORKSPACE", -5: "SM_ERR_HIP", -6: "SM_ERR_UNSORTED"}
 

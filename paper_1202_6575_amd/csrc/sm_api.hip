@@ -37,9 +37,9 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(SM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-size_t key_bytes(int dtype) { return dtype == SM_UINT64 ? 8 : 4; }
+size_t key_bytes(int dtype) { return sm::dtype_bytes(dtype); }
 
-bool dtype_ok(int dtype) { return dtype == SM_INT32 || dtype == SM_UINT32 || dtype == SM_UINT64; }
+bool dtype_ok(int dtype) { return sm::dtype_known(dtype); }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
@@ -56,7 +56,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // length (measured on MI355X) at which four merge workgroups still share a
 // compute unit's 160 KiB of LDS.
 int32_t default_tile(int dtype, bool pay) {
-    if (dtype == SM_UINT64) return pay ? 1024 : 1152;
+    if (key_bytes(dtype) == 8) return pay ? 1024 : 1152;
     return pay ? 1152 : 2368;
 }
 

@@ -288,12 +288,6 @@ __global__ void clear_kernel(int* __restrict__ p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-template <typename F>
-static void with_dtype(int dtype, F&& f) {
-    if (dtype == 0) f((int32_t)0);
-    else if (dtype == 1) f((uint32_t)0);
-    else f((uint64_t)0);
-}
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -335,7 +329,7 @@ hipError_t launch_batch_validate(int dtype, const void* keys, const int64_t* off
     int64_t g = (total + 255) / 256;
     const int64_t gmax = (int64_t)device_cu_count() * 8;
     if (g > gmax) g = gmax;
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         batch_validate_kernel<K><<<(unsigned)g, 256, 0, st>>>(static_cast<const K*>(keys), offsets,
                                                               n_a, count, bad);
@@ -376,7 +370,7 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
     const int64_t grid = (int64_t)device_cu_count() * 8;
     int64_t gs = (L.s_max + 255) / 256;
     if (gs > grid) gs = grid;
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         batch_partition_kernel<K><<<(unsigned)gs, 256, 0, st>>>(static_cast<const K*>(keys), jobs,
                                                                 count, tile, cap, sstart, totals,

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sm_keys.h"
+
 namespace sm {
 
 // ---------------------------------------------------------------------------
@@ -221,11 +223,6 @@ __host__ __device__ inline int desc_b(const PieceDesc& d) { return (int)(d.b_f &
 template <typename K>
 struct Vec { static constexpr int N = 16 / sizeof(K); };
 
-template <typename K>
-struct KeyMax;
-template <> struct KeyMax<int32_t> { static constexpr int32_t v = 0x7fffffff; };
-template <> struct KeyMax<uint32_t> { static constexpr uint32_t v = 0xffffffffu; };
-template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = ~0ull; };
 
 // rank_low / rank_high of x over X[0, n) in LDS, branch-free (the halving
 // length is workgroup-uniform, so only the base moves per lane): the answer

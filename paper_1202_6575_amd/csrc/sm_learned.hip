@@ -38,6 +38,12 @@ __device__ __forceinline__ float feature(uint32_t x) {
 __device__ __forceinline__ float feature(uint64_t x) {
     return log2f((float)x + 1.0f) * (1.0f / 64.0f);
 }
+__device__ __forceinline__ float feature(int64_t x) {
+    return feature((uint64_t)((uint64_t)x ^ 0x8000000000000000ull));
+}
+// floats: the position in totalOrder, as an unsigned integer of the same width
+__device__ __forceinline__ float feature(KeyF32 x) { return feature(order_bits(x)); }
+__device__ __forceinline__ float feature(KeyF64 x) { return feature(order_bits(x)); }
 
 // y = b2 + sum_k w2[k] * ReLU(W1[k] * phi + b1[k]); parameters W1[0:32],
 // b1[32:64], w2[64:96], b2[96].
@@ -413,12 +419,6 @@ __global__ __launch_bounds__(256) void learned_partition_kernel(
     if (threadIdx.x < 3 && sc[threadIdx.x]) atomicAdd(&counters[threadIdx.x], sc[threadIdx.x]);
 }
 
-template <typename F>
-void with_key(int dtype, F&& f) {
-    if (dtype == 0) f((int32_t)0);
-    else if (dtype == 1) f((uint32_t)0);
-    else f((uint64_t)0);
-}
 
 unsigned grid_for(int64_t items, int64_t cap_blocks) {
     int64_t g = (items + 255) / 256;
@@ -445,7 +445,7 @@ hipError_t launch_mlp_grad(int dtype, const float* P, const void* keys, const fl
     const int64_t blocks = mlp_grad_blocks(S);
     const int64_t per_block = (S + blocks - 1) / blocks;
     float* partial = static_cast<float*>(ws);
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         mlp_grad_kernel<K><<<(unsigned)blocks, kGradThreads, 0, st>>>(
             P, static_cast<const K*>(keys), target, S, per_block > 0 ? per_block : 1, partial);
@@ -466,7 +466,7 @@ hipError_t launch_mlp_adam(float* P, float* M, float* V, const float* G, int64_t
 
 hipError_t launch_mlp_init(int dtype, const void* sorted_keys, const float* target, int64_t S,
                            float* P, hipStream_t st) {
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         mlp_init_kernel<K><<<1, 64, 0, st>>>(static_cast<const K*>(sorted_keys), target, S, P);
     });
@@ -476,7 +476,7 @@ hipError_t launch_mlp_init(int dtype, const void* sorted_keys, const float* targ
 hipError_t launch_mlp_predict(int dtype, const float* P, const void* keys, int64_t q, int64_t len,
                               int64_t* rhat, hipStream_t st) {
     if (q <= 0) return hipSuccess;
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         mlp_predict_kernel<K><<<grid_for(q, 8192), 256, 0, st>>>(P, static_cast<const K*>(keys), q,
                                                                   len, rhat);
@@ -488,7 +488,7 @@ hipError_t launch_rank_search(int dtype, const void* X, int64_t len, const void*
                               int is_high, const int64_t* guess, int64_t step0, int64_t window,
                               int64_t* ranks, int32_t* probes, int32_t* fallback, hipStream_t st) {
     if (q <= 0) return hipSuccess;
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         rank_search_kernel<K><<<grid_for(q, 8192), 256, 0, st>>>(
             static_cast<const K*>(X), len, static_cast<const K*>(queries), q, is_high, guess, step0,
@@ -508,7 +508,7 @@ hipError_t launch_learned_partition(int dtype, const void* keys, int64_t n, int6
     // spends the time on the per-workgroup counter atomics (measured 1.26,
     // 1.19 and 1.75 ms)
     const unsigned grid = grid_for(p_a + p_b + 2, (int64_t)device_cu_count() * 64);
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         learned_partition_kernel<K><<<grid, 256, 0, st>>>(
             static_cast<const K*>(keys), n, m, p_a, p_b, model_b, model_a, step0_a, step0_b, window,
@@ -520,7 +520,7 @@ hipError_t launch_learned_partition(int dtype, const void* keys, int64_t n, int6
 
 RankModelLayout rank_model_layout(int64_t S, int dtype) {
     RankModelLayout L;
-    const size_t kb = dtype == 2 ? 8 : 4;
+    const size_t kb = (int)dtype_bytes(dtype);
     size_t off = 0;
     L.off_keys = off; off += align256((size_t)S * kb);
     L.off_target = off; off += align256((size_t)S * 4);
@@ -542,7 +542,7 @@ hipError_t launch_rank_model_train(int dtype, const void* X, int64_t len, const 
     float* grad = reinterpret_cast<float*>(ws + L.off_grad);
     float* M = reinterpret_cast<float*>(ws + L.off_m);
     float* V = reinterpret_cast<float*>(ws + L.off_v);
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         rank_sample_kernel<K><<<grid_for(S, 4096), 256, 0, st>>>(
             static_cast<const K*>(X), len, static_cast<const K*>(Q), q_len, is_high, S, seed,

@@ -434,16 +434,10 @@ __global__ __launch_bounds__(256) void validate_kernel(const K* __restrict__ key
 
 // ---------------------------------------------------------------------------
 
-template <typename F>
-static void with_dtype(int dtype, F&& f) {
-    if (dtype == 0) f((int32_t)0);
-    else if (dtype == 1) f((uint32_t)0);
-    else f((uint64_t)0);
-}
 
 uint32_t merge_lds_bytes(int dtype, bool pay, uint32_t cap) {
     uint32_t r = 0;
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         r = pay ? MergeSmem<K, true, kMergeThreads>::bytes(cap)
                 : MergeSmem<K, false, kMergeThreads>::bytes(cap);
@@ -455,7 +449,7 @@ hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m, i
                             int64_t p_b, int64_t* xbar, int64_t* ybar, hipStream_t st) {
     const int64_t threads = p_a + p_b + 2;
     const unsigned grid = (unsigned)((threads + 255) / 256);
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         partition_kernel<K><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), n, m, p_a, p_b,
                                                   xbar, ybar);
@@ -624,7 +618,7 @@ hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, i
                              const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
                              hipStream_t st) {
     hipError_t e = hipSuccess;
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         e = pay ? launch_merge_t<K, true>(keys, pay, nkeys, out_keys, out_pay, nout, desc, P, P_dev,
                                           cap, st)
@@ -645,7 +639,7 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
     // does not fit, nothing is staged); a workgroup whose ranges exceed the
     // capacity merges from global memory
     const int64_t la_max = (n + p_a - 1) / p_a;
-    const int ksz = dtype == 2 ? 8 : 4;
+    const int ksz = (int)dtype_bytes(dtype);
     const int esz = ksz + (pay ? 4 : 0);
     int capA = (int)(kFineG * (la_max > 0 ? la_max : 1));
     int capB = 2 * capA > 2048 ? 2 * capA : 2048;
@@ -654,7 +648,7 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
     if (FineSmem(capA, capB).bytes_for(esz) > kFineLds) capA = capB = 0;
     const FineSmem fs(capA, capB);
     hipError_t e = hipSuccess;
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         const uint32_t lds = fs.bytes_for(esz);
         if (pay) {
@@ -685,7 +679,7 @@ hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, in
     int64_t g = (total + 255) / 256;
     if (g > 4096) g = 4096;
     if (g < 1) g = 1;
-    with_dtype(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         validate_kernel<K><<<(unsigned)g, 256, 0, st>>>(static_cast<const K*>(keys), n, m, flag);
     });

@@ -114,12 +114,6 @@ __global__ __launch_bounds__(256) void sort_pass_jobs_kernel(int64_t N, int64_t 
     }
 }
 
-template <typename F>
-void with_key(int dtype, F&& f) {
-    if (dtype == 0) f((int32_t)0);
-    else if (dtype == 1) f((uint32_t)0);
-    else f((uint64_t)0);
-}
 
 template <typename K, bool PAY>
 hipError_t launch_runs_t(const K* keys, const uint32_t* pay, int64_t N, K* out, uint32_t* out_pay,
@@ -148,7 +142,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 bool sort_run_ok(int run, int dtype) {
-    return run == 256 || run == 512 || run == 1024 || run == 2048 || (run == 4096 && dtype != 2);
+    return run == 256 || run == 512 || run == 1024 || run == 2048 || (run == 4096 && dtype_bytes(dtype) == 4);
 }
 
 int sort_passes(int64_t N, int run) {
@@ -159,7 +153,7 @@ int sort_passes(int64_t N, int run) {
 
 SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile) {
     SortLayout L;
-    const size_t kb = dtype == 2 ? 8 : 4;
+    const size_t kb = (int)dtype_bytes(dtype);
     L.passes = sort_passes(N, run);
     L.count_max = N > run ? (N + 2 * (int64_t)run - 1) / (2 * (int64_t)run) : 1;
     size_t off = 0;
@@ -188,7 +182,7 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
     char* dst_k = runs_to_out ? tmp_k : static_cast<char*>(out_keys);
     uint32_t* dst_p = runs_to_out ? tmp_p : out_pay;
     hipError_t e = hipSuccess;
-    with_key(dtype, [&](auto z) {
+    with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         e = pay ? launch_runs_t<K, true>(static_cast<const K*>(keys), pay, N,
                                          reinterpret_cast<K*>(src_k), src_p, run, st)

@@ -100,7 +100,7 @@ def test_batched_error_paths(sm):
         a = dict(args, **kw)
         return f(a["keys"], a["pay"], a["offs"], a["na"], a["count"], a["total"], a["out"],
                  a["opay"], a["dtype"], a["ws"], a["ws_bytes"], ctypes.byref(o), None)
-    assert call(dtype=5) == -2
+    assert call(dtype=6) == -2
     assert call(count=-1) == -1
     assert call(offs=None) == -1
     assert call(out=0x10000) == -3

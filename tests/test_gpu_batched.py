@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_1202_6575_amd as sm  # noqa: E402
 
-DTYPES = [np.int32, np.uint32, np.uint64]
+DTYPES = [np.int32, np.uint32, np.uint64, np.int64, np.float32, np.float64]
 
 
 def make_batch(g, lengths, alpha, dtype, gap=0):

@@ -13,14 +13,14 @@ import torch
 
 import datagen
 import oracle
-from helpers import dev, flush, host, rand_sorted
+from helpers import total_order_sequence, dev, flush, host, rand_sorted
 
 pytestmark = pytest.mark.gpu
 
 import paper_1202_6575_amd as sm  # noqa: E402
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "figure1.json")
-DTYPES = [np.int32, np.uint32, np.uint64]
+DTYPES = [np.int32, np.uint32, np.uint64, np.int64, np.float32, np.float64]
 
 
 def run_merge(A, B, pa=None, pb=None, **kw):
@@ -197,6 +197,24 @@ def test_small_blocks_staging_limits(dtype, with_pay):
             B = np.sort(np.concatenate([B[: m // 2], np.full(m - m // 2, A[n // 2], dtype)]))
         flush(f"staging limits dtype={np.dtype(dtype).name} pay={with_pay} n={n} m={m} {kw}")
         check(A, B, with_pay, **kw)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_float_total_order_merge(dt):
+    """Float keys merge in IEEE 754 totalOrder: specials (NaNs of both signs,
+    infinities, -0 before +0, subnormals) sorted by the oracle, then merged
+    on the GPU with payloads at several block lengths, against the oracle."""
+    seq = total_order_sequence(dt)
+    g = np.random.default_rng(17)
+    for n, m in [(3000, 2000), (100_003, 7), (1, 40_000)]:
+        A, _ = oracle.sort(seq[g.integers(0, len(seq), size=n)], None, 512)
+        B, _ = oracle.sort(seq[g.integers(0, len(seq), size=m)], None, 512)
+        for kw in (dict(), dict(tile=1), dict(tile=16), dict(p_a=3, p_b=5)):
+            flush(f"float total order {np.dtype(dt).name} n={n} m={m} {kw}")
+            ck, cp = run_merge(A, B, *datagen.source_tag_payloads(n, m), **kw)
+            rk, rp = oracle.merge(A, B, *datagen.source_tag_payloads(n, m))
+            ut = np.uint32 if dt == np.float32 else np.uint64
+            assert np.array_equal(ck.view(ut), rk.view(ut)) and np.array_equal(cp, rp)
 
 
 def test_validate_detects_unsorted():

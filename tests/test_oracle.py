@@ -21,9 +21,10 @@ import pytest
 
 import oracle
 from oracle import mlp
+from helpers import total_order_sequence
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "figure1.json")
-DTYPES = [np.int32, np.uint32, np.uint64]
+DTYPES = [np.int32, np.uint32, np.uint64, np.int64, np.float32, np.float64]
 
 
 def fig1():
@@ -34,7 +35,7 @@ def fig1():
 
 def brute_merge(A, B, pa=None, pb=None):
     """Stable merge by sorting (key, source, index) tags with Python's sort."""
-    tags = [(int(a), 0, i) for i, a in enumerate(A)] + [(int(b), 1, j) for j, b in enumerate(B)]
+    tags = [(a.item(), 0, i) for i, a in enumerate(A)] + [(b.item(), 1, j) for j, b in enumerate(B)]
     tags.sort()
     keys = np.array([t[0] for t in tags], dtype=A.dtype) if tags else np.zeros(0, A.dtype)
     if pa is None:
@@ -55,6 +56,13 @@ def rand_sorted(g, n, alphabet, dtype):
         x = g.integers(-alphabet // 2, alphabet - alphabet // 2, size=n).astype(np.int32)
     elif dtype == np.uint32:
         x = (g.integers(0, alphabet, size=n) + (2 ** 32 - alphabet) * g.integers(0, 2)).astype(np.uint32)
+    elif dtype == np.int64:
+        # both signs, magnitudes beyond 32 bits
+        x = (g.integers(-alphabet // 2, alphabet - alphabet // 2, size=n).astype(np.int64)
+             * np.int64(0x0100000001))
+    elif dtype in (np.float32, np.float64):
+        # no NaN and no -0: numeric order is the totalOrder here
+        x = (g.integers(-alphabet // 2, alphabet - alphabet // 2, size=n) * 0.375).astype(dtype)
     else:
         x = (g.integers(0, alphabet, size=n).astype(np.uint64) * np.uint64(0x0100000000000001))
     x.sort()
@@ -494,6 +502,41 @@ def test_mlp_features_order_preserving():
     assert (np.diff(f) > 0).all() and f[0] == 0.0
     ku = np.array([0, 1, 2 ** 32 - 1], dtype=np.uint32)
     assert np.isclose(mlp.features(ku)[-1], 1.0)
+    k64 = np.array([-2 ** 63, -1, 0, 1, 2 ** 63 - 1], dtype=np.int64)
+    u64 = [int(v) for v in mlp.unsigned_order(k64)]
+    assert u64 == [0, 2 ** 63 - 1, 2 ** 63, 2 ** 63 + 1, 2 ** 64 - 1]
+    for dt in (np.float32, np.float64):
+        seq = total_order_sequence(dt)
+        u = mlp.unsigned_order(seq)
+        assert all(int(u[i]) < int(u[i + 1]) for i in range(len(u) - 1))
+        assert int(u[0]) == 0 and int(u[-1]) == 2 ** (8 * seq.itemsize) - 1
+
+
+# --------------------------------------------------------------------------
+# Float keys: IEEE 754 totalOrder
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_float_total_order(dt):
+    """The oracle's sort of shuffled specials gives back the totalOrder
+    sequence bit for bit (-0 strictly before +0, NaNs by sign and payload);
+    finite non-zero values follow numeric order; a merge of two sorted
+    subsets equals the sorted union."""
+    seq = total_order_sequence(dt)
+    ut = np.uint32 if dt == np.float32 else np.uint64
+    g = np.random.default_rng(21)
+    for _ in range(20):
+        perm = g.permutation(len(seq))
+        k, _ = oracle.sort(seq[perm], np.arange(len(seq), dtype=np.uint32), 4)
+        assert np.array_equal(k.view(ut), seq.view(ut))
+        take = np.sort(g.choice(len(seq), size=len(seq) // 2, replace=False))
+        rest = np.setdiff1d(np.arange(len(seq)), take)
+        c, _ = oracle.merge(seq[take], seq[rest])
+        assert np.array_equal(c.view(ut), seq.view(ut))
+    vals = (g.standard_normal(500) * 10.0 ** g.integers(-30, 30, 500)).astype(dt)
+    vals = vals[vals != 0]
+    k, _ = oracle.sort(vals, np.arange(len(vals), dtype=np.uint32), 64)
+    assert np.array_equal(k, np.sort(vals))
 
 
 def test_error_bins():
