@@ -201,6 +201,33 @@ SM_API int stable_merge_sort(const void *keys, const uint32_t *payloads, int64_t
                              void *out_keys, uint32_t *out_payloads, int dtype,
                              void *ws, size_t ws_bytes, const sm_options *opt, void *stream);
 
+/*
+ * Segmented stable sort: every segment keys[offsets[s], offsets[s + 1]) is
+ * sorted on its own, payloads (optional) travelling with their keys and
+ * equal keys keeping their input order, as stable_merge_sort would sort it
+ * alone.  offsets holds count + 1 device int64 entries running from 0 to N
+ * without decreasing; no segment may be longer than max_len (a host-side
+ * bound, which fixes the number of merge passes: ceil(log2(max_len / run))).
+ * Runs start at segment starts, and every merge pass pairs runs within a
+ * segment.  The host never reads offsets, so the call can be captured in a
+ * graph; with options.validate set it checks offsets and max_len first and
+ * returns SM_ERR_ARG (otherwise a violation leaves the output undefined).
+ * 1 <= count < 2^31, 0 <= max_len <= N < 2^31; buffers, aliasing and
+ * options.run as for stable_merge_sort; ws must hold
+ * stable_merge_segmented_sort_workspace_bytes() bytes.
+ */
+SM_API int stable_merge_segmented_sort(const void *keys, const uint32_t *payloads,
+                                       const int64_t *offsets, int64_t count, int64_t N,
+                                       int64_t max_len, void *out_keys, uint32_t *out_payloads,
+                                       int dtype, void *ws, size_t ws_bytes,
+                                       const sm_options *opt, void *stream);
+
+/* Device workspace bytes of stable_merge_segmented_sort (0 on bad arguments). */
+SM_API size_t stable_merge_segmented_sort_workspace_bytes(int64_t count, int64_t N,
+                                                          int64_t max_len, int dtype,
+                                                          int has_payload,
+                                                          const sm_options *opt);
+
 /* Device workspace bytes of stable_merge_sort (0 on bad arguments). */
 SM_API size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_payload,
                                                 const sm_options *opt);

@@ -22,8 +22,10 @@ import os
 
 import torch
 
-__all__ = ["merge", "partition", "merge_pieces", "merge_batched", "sort", "workspace_bytes",
-           "pieces_workspace_bytes", "batched_workspace_bytes", "sort_workspace_bytes", "SMError", "LIB_PATH", "DTYPES"]
+__all__ = ["merge", "partition", "merge_pieces", "merge_batched", "sort", "segmented_sort",
+           "workspace_bytes", "pieces_workspace_bytes", "batched_workspace_bytes",
+           "sort_workspace_bytes", "segmented_sort_workspace_bytes", "SMError", "LIB_PATH",
+           "DTYPES"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstablemerge.so")
 
@@ -79,6 +81,12 @@ _lib.stable_merge_sort.argtypes = [_vp, _vp, _i64, _vp, _vp, _i32, _vp, _sz,
                                    ctypes.POINTER(Options), _vp]
 _lib.stable_merge_sort_workspace_bytes.restype = _sz
 _lib.stable_merge_sort_workspace_bytes.argtypes = [_i64, _i32, _i32, ctypes.POINTER(Options)]
+_lib.stable_merge_segmented_sort.restype = _i32
+_lib.stable_merge_segmented_sort.argtypes = [_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _i32, _vp,
+                                             _sz, ctypes.POINTER(Options), _vp]
+_lib.stable_merge_segmented_sort_workspace_bytes.restype = _sz
+_lib.stable_merge_segmented_sort_workspace_bytes.argtypes = [_i64, _i64, _i64, _i32, _i32,
+                                                             ctypes.POINTER(Options)]
 _lib.stable_merge_partition.restype = _i32
 _lib.stable_merge_partition.argtypes = [_vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp]
 
@@ -266,4 +274,41 @@ def sort(keys: torch.Tensor, payloads: torch.Tensor | None = None, *,
     _check(_lib.stable_merge_sort(_ptr(keys), _ptr(payloads), N, _ptr(out_keys),
                                   _ptr(out_payloads), code, _ptr(workspace), workspace.numel(),
                                   ctypes.byref(o), _stream_ptr(stream)))
+    return out_keys, out_payloads
+
+
+def segmented_sort_workspace_bytes(count: int, N: int, max_len: int, dtype: torch.dtype,
+                                   has_payload: bool = False, run: int = 0, tile: int = 0) -> int:
+    """Device workspace bytes stable_merge_segmented_sort needs (0 on bad arguments)."""
+    o = _opts(0, 0, tile, False, run)
+    return int(_lib.stable_merge_segmented_sort_workspace_bytes(
+        count, N, max_len, DTYPES[dtype], int(has_payload), ctypes.byref(o)))
+
+
+def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, max_len: int,
+                   payloads: torch.Tensor | None = None, *, out_keys: torch.Tensor | None = None,
+                   out_payloads: torch.Tensor | None = None, run: int = 0, tile: int = 0,
+                   validate: bool = False, workspace: torch.Tensor | None = None, stream=None):
+    """Stable sort of every segment keys[offsets[s]:offsets[s+1]] on its own.
+    offsets is a device int64 tensor of count + 1 entries from 0 to N; max_len
+    bounds the segment lengths (host value).  Returns (out_keys, out_payloads)."""
+    _require_device(keys, offsets, payloads, out_keys, out_payloads, workspace)
+    if offsets.dtype != torch.int64:
+        raise SMError(-1, "offsets must be int64")
+    N = keys.numel()
+    count = offsets.numel() - 1
+    code = _dtype_code(keys)
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(N, dtype=torch.uint32, device=keys.device)
+    o = _opts(0, 0, tile, validate, run)
+    if workspace is None:
+        need = int(_lib.stable_merge_segmented_sort_workspace_bytes(
+            count, N, max_len, code, int(payloads is not None), ctypes.byref(o)))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=keys.device)
+    _check(_lib.stable_merge_segmented_sort(_ptr(keys), _ptr(payloads), _ptr(offsets), count, N,
+                                            max_len, _ptr(out_keys), _ptr(out_payloads), code,
+                                            _ptr(workspace), workspace.numel(), ctypes.byref(o),
+                                            _stream_ptr(stream)))
     return out_keys, out_payloads

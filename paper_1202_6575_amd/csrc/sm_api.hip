@@ -352,7 +352,7 @@ int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64
 namespace {
 
 int sort_plan(int64_t N, int dtype, bool pay, const sm_options* opt, int* run, int32_t* tile,
-              sm::SortLayout* L) {
+              sm::SortLayout* L, int64_t seg_count = 0, int64_t max_len = 0) {
     if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
     if (N < 0 || N >= (1ll << 31)) return fail(SM_ERR_ARG, "N must be in [0, 2^31)");
     *run = opt && opt->run != 0 ? opt->run : 512;
@@ -361,7 +361,7 @@ int sort_plan(int64_t N, int dtype, bool pay, const sm_options* opt, int* run, i
     *tile = pick_tile(dtype, pay, opt);
     int rc = check_tile(dtype, pay, *tile);
     if (rc != SM_OK) return rc;
-    *L = sm::sort_layout(N, dtype, pay, *run, *tile);
+    *L = sm::sort_layout(N, dtype, pay, *run, *tile, seg_count, max_len);
     if (L->batch.p_max > (1ll << 31) - 2)
         return fail(SM_ERR_ARG, "too many subproblems per pass; use a larger tile");
     return SM_OK;
@@ -378,6 +378,40 @@ size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_payload,
     return L.bytes;
 }
 
+namespace {
+
+// Argument checks shared by the two sorts (after sort_plan).
+int check_sort_buffers(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                       uint32_t* out_payloads, int dtype, const void* ws, size_t ws_bytes,
+                       size_t need) {
+    const bool pay = payloads != nullptr;
+    if ((payloads == nullptr) != (out_payloads == nullptr))
+        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
+    if (!keys || !out_keys) return fail(SM_ERR_ARG, "keys and out_keys must not be NULL");
+    if (!aligned16(keys) || !aligned16(out_keys) ||
+        (pay && (!aligned16(payloads) || !aligned16(out_payloads))))
+        return fail(SM_ERR_ARG, "device arrays must be 16-byte aligned");
+    const size_t kb = (size_t)N * key_bytes(dtype), pb = (size_t)N * 4;
+    // the same array in and out is an in-place sort; a partial overlap is not
+    if ((out_keys != keys && overlap(out_keys, kb, keys, kb)) ||
+        (pay && ((out_payloads != payloads && overlap(out_payloads, pb, payloads, pb)) ||
+                 overlap(out_payloads, pb, keys, kb) || overlap(out_keys, kb, payloads, pb) ||
+                 overlap(out_keys, kb, out_payloads, pb))))
+        return fail(SM_ERR_ALIAS, "outputs overlap inputs other than in place");
+    int rc = check_ws(ws, ws_bytes, need);
+    if (rc != SM_OK) return rc;
+    const char* w = static_cast<const char*>(ws);
+    if (overlap(w, need, keys, kb) || overlap(w, need, out_keys, kb) ||
+        (pay && (overlap(w, need, payloads, pb) || overlap(w, need, out_payloads, pb))))
+        return fail(SM_ERR_ALIAS, "workspace overlaps the keys or payloads");
+    return SM_OK;
+}
+
+// The segmented sort's workspace: the sort's, then one status word.
+size_t seg_flag_offset(const sm::SortLayout& L) { return align256(L.bytes); }
+
+}  // namespace
+
 int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
                       uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
                       const sm_options* opt, void* stream) {
@@ -390,26 +424,65 @@ int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, voi
     if ((payloads == nullptr) != (out_payloads == nullptr))
         return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
     if (N == 0) return SM_OK;
-    if (!keys || !out_keys) return fail(SM_ERR_ARG, "keys and out_keys must not be NULL");
-    if (!aligned16(keys) || !aligned16(out_keys) ||
-        (pay && (!aligned16(payloads) || !aligned16(out_payloads))))
-        return fail(SM_ERR_ARG, "device arrays must be 16-byte aligned");
-    const size_t kb = (size_t)N * key_bytes(dtype), pb = (size_t)N * 4;
-    // the same array in and out is an in-place sort; a partial overlap is not
-    if ((out_keys != keys && overlap(out_keys, kb, keys, kb)) ||
-        (pay && ((out_payloads != payloads && overlap(out_payloads, pb, payloads, pb)) ||
-                 overlap(out_payloads, pb, keys, kb) || overlap(out_keys, kb, payloads, pb) ||
-                 overlap(out_keys, kb, out_payloads, pb))))
-        return fail(SM_ERR_ALIAS, "outputs overlap inputs other than in place");
-    rc = check_ws(ws, ws_bytes, L.bytes);
+    rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
+                            L.bytes);
     if (rc != SM_OK) return rc;
-    const char* w = static_cast<const char*>(ws);
-    if (overlap(w, L.bytes, keys, kb) || overlap(w, L.bytes, out_keys, kb) ||
-        (pay && (overlap(w, L.bytes, payloads, pb) || overlap(w, L.bytes, out_payloads, pb))))
-        return fail(SM_ERR_ALIAS, "workspace overlaps the keys or payloads");
     hipError_t e = sm::launch_sort(dtype, keys, payloads, N, out_keys, out_payloads, run, tile,
                                    static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "sort launch");
+    return SM_OK;
+}
+
+size_t stable_merge_segmented_sort_workspace_bytes(int64_t count, int64_t N, int64_t max_len,
+                                                   int dtype, int has_payload,
+                                                   const sm_options* opt) {
+    int run;
+    int32_t tile;
+    sm::SortLayout L;
+    if (count < 1 || max_len < 0 || max_len > N) return 0;
+    if (sort_plan(N, dtype, has_payload != 0, opt, &run, &tile, &L, count, max_len) != SM_OK)
+        return 0;
+    return seg_flag_offset(L) + 256;
+}
+
+int stable_merge_segmented_sort(const void* keys, const uint32_t* payloads,
+                                const int64_t* offsets, int64_t count, int64_t N,
+                                int64_t max_len, void* out_keys, uint32_t* out_payloads,
+                                int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
+                                void* stream) {
+    const bool pay = payloads != nullptr;
+    if (count < 1) return fail(SM_ERR_ARG, "count must be >= 1");
+    if (count > (1ll << 31)) return fail(SM_ERR_ARG, "count must be below 2^31");
+    if (max_len < 0 || max_len > N) return fail(SM_ERR_ARG, "0 <= max_len <= N required");
+    int run;
+    int32_t tile;
+    sm::SortLayout L;
+    int rc = sort_plan(N, dtype, pay, opt, &run, &tile, &L, count, max_len);
+    if (rc != SM_OK) return rc;
+    if ((payloads == nullptr) != (out_payloads == nullptr))
+        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
+    if (!offsets) return fail(SM_ERR_ARG, "offsets must not be NULL");
+    if (N == 0) return SM_OK;
+    const size_t need = seg_flag_offset(L) + 256;
+    rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes, need);
+    if (rc != SM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (opt && opt->validate) {
+        int* flag = reinterpret_cast<int*>(static_cast<char*>(ws) + seg_flag_offset(L));
+        int host_flag = 0;
+        hipError_t e = sm::launch_clear(flag, 1, st);
+        if (e == hipSuccess) e = sm::launch_seg_check(offsets, count, N, max_len, flag, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&host_flag, flag, sizeof(int),
+                                                hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "segment check");
+        if (host_flag)
+            return fail(SM_ERR_ARG, "offsets must run from 0 to N without decreasing, with no "
+                                    "segment longer than max_len");
+    }
+    hipError_t e = sm::launch_sort(dtype, keys, payloads, N, out_keys, out_payloads, run, tile,
+                                   static_cast<char*>(ws), L, st, offsets, count);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
     return SM_OK;
 }
 

@@ -33,7 +33,7 @@ __device__ __forceinline__ void job_counts(const PieceDesc& j, int64_t tile, uin
                                            int64_t& p_b) {
     const int64_t a = desc_a(j), b = desc_b(j);
     if (a + b <= (int64_t)cap) {
-        pieces = 1;
+        pieces = a + b > 0 ? 1 : 0;   // an empty job costs no merge step
         splitters = 0;
         p_a = p_b = 0;
         return;

@@ -24,12 +24,24 @@ bool sort_run_ok(int run, int dtype);
 // Number of merge passes after runs of `run` elements: ceil(log2(N / run)).
 int sort_passes(int64_t N, int run);
 
-SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile);
+// seg_count > 0: the segmented sort of seg_count segments no longer than
+// max_len each.
+SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile,
+                       int64_t seg_count = 0, int64_t max_len = 0);
 
 // Run formation, then the merge passes; the result lands in out_keys /
 // out_pay, which may be the input arrays themselves.
+// With seg_offsets (device, seg_count + 1 entries from 0 to N) every
+// segment is sorted on its own: runs start at segment starts and every merge
+// pass pairs runs within a segment.
 hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t N, void* out_keys,
                        uint32_t* out_pay, int run, int64_t tile, char* ws, const SortLayout& L,
-                       hipStream_t st);
+                       hipStream_t st, const int64_t* seg_offsets = nullptr,
+                       int64_t seg_count = 0);
+
+// Sets *bad (device int, cleared beforehand) unless the offsets run from 0
+// to N without decreasing and no segment is longer than max_len.
+hipError_t launch_seg_check(const int64_t* offsets, int64_t count, int64_t N, int64_t max_len,
+                            int* bad, hipStream_t st);
 
 }  // namespace sm

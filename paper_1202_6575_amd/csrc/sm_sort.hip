@@ -34,23 +34,54 @@ struct RunSmem {
     uint32_t pay[PAY ? 2 : 1][PAY ? RUN : 1];
 };
 
-// Stable sort of keys[r0, r0 + len) (len <= RUN) into out[r0, r0 + len).
+// Segments (the segmented sort): segment s is [offsets[s], offsets[s + 1]).
+// Work item k of segment s at width W (its k-th run, or its k-th pair of
+// runs) gets the slot s + floor(offsets[s] / W) + k.  This is one-to-one
+// over k < ceil(len_s / W): the first slot of segment s + 1 is at least
+// 1 + floor(offsets[s + 1] / W), beyond the last slot of segment s.  So
+// count + N / W + 1 slots cover every item, and a slot finds its segment
+// by binary search, with no prefix sums.  Returns false for a slot that
+// holds no item.
+__device__ __forceinline__ bool seg_slot(const int64_t* __restrict__ offsets, int64_t count,
+                                         int64_t W, int64_t t, int64_t& seg, int64_t& k) {
+    if (count <= 0 || offsets[0] / W > t) return false;
+    int64_t lo = 0, hi = count - 1;   // last s with s + offsets[s] / W <= t
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (mid + offsets[mid] / W <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    seg = lo;
+    k = t - (lo + offsets[lo] / W);
+    const int64_t len = offsets[lo + 1] - offsets[lo];
+    return k < (len + W - 1) / W;
+}
+
+// Stable sort of keys[r0, r0 + len) (len <= RUN) into out[r0, r0 + len):
+// r0 = blockIdx.x * RUN without segments; with segments, the block's slot
+// names a run of a segment, which starts at the segment's start.
 // Positions past len hold the largest key; they start behind every real
 // element and every round keeps them there (a right element ties behind the
 // whole left piece), so the real elements' order is the stable one.
 template <typename K, bool PAY, int RUN>
 // keys / out (and pay / out_pay) may be the same array: a workgroup reads
 // its whole run before it writes any of it.
-__global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(const K* keys, const uint32_t* pay,
-                                                                int64_t N, K* out,
-                                                                uint32_t* out_pay) {
+__global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(
+    const K* keys, const uint32_t* pay, int64_t N, K* out, uint32_t* out_pay,
+    const int64_t* __restrict__ seg_offsets, int64_t seg_count) {
     constexpr int T = run_threads<RUN>();
     constexpr int E = RUN / T;
     static_assert(RUN % T == 0 && (RUN & (RUN - 1)) == 0, "RUN: power of two, multiple of T");
     __shared__ RunSmem<K, PAY, RUN> s;
     const int t = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * RUN;
-    const int64_t rem = N - r0;
+    int64_t r0 = (int64_t)blockIdx.x * RUN, end = N;
+    if (seg_offsets) {
+        int64_t sg, r;
+        if (!seg_slot(seg_offsets, seg_count, RUN, blockIdx.x, sg, r)) return;
+        r0 = seg_offsets[sg] + r * RUN;
+        end = seg_offsets[sg + 1];
+    }
+    const int64_t rem = end - r0;
     const int len = rem < RUN ? (int)rem : RUN;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -115,19 +146,66 @@ __global__ __launch_bounds__(256) void sort_pass_jobs_kernel(int64_t N, int64_t 
 }
 
 
+// Jobs of merge pass w of the segmented sort: slot t (at width 2w) holds
+// pair k of segment s: [lo, lo + w) with [lo + w, lo + 2w), clipped to the
+// segment, lo = offsets[s] + 2kw; a slot with no pair is an empty job.
+__global__ __launch_bounds__(256) void seg_pass_jobs_kernel(const int64_t* __restrict__ offsets,
+                                                            int64_t count, int64_t w,
+                                                            int64_t nslots,
+                                                            PieceDesc* __restrict__ jobs) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nslots;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        PieceDesc j;
+        j.ka0 = j.kb0 = j.out0 = 0;
+        j.a_f = j.b_f = 0;
+        int64_t sg, k;
+        if (seg_slot(offsets, count, 2 * w, t, sg, k)) {
+            const int64_t end = offsets[sg + 1];
+            const int64_t lo = offsets[sg] + 2 * k * w;
+            const int64_t mid = lo + w < end ? lo + w : end;
+            const int64_t hi = lo + 2 * w < end ? lo + 2 * w : end;
+            j.ka0 = lo;
+            j.kb0 = mid;
+            j.out0 = lo;
+            j.a_f = (uint32_t)(mid - lo);
+            j.b_f = (uint32_t)(hi - mid);
+        }
+        jobs[t] = j;
+    }
+}
+
+// Sets *bad unless offsets run from 0 to N without decreasing and no segment
+// is longer than max_len.
+__global__ __launch_bounds__(256) void seg_check_kernel(const int64_t* __restrict__ offsets,
+                                                        int64_t count, int64_t N, int64_t max_len,
+                                                        int* __restrict__ bad) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < count;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = offsets[s], b = offsets[s + 1];
+        if (b < a || b - a > max_len || (s == 0 && a != 0) || (s == count - 1 && b != N))
+            *bad = 1;
+    }
+}
+
 template <typename K, bool PAY>
 hipError_t launch_runs_t(const K* keys, const uint32_t* pay, int64_t N, K* out, uint32_t* out_pay,
-                         int run, hipStream_t st) {
-    const int64_t g = (N + run - 1) / run;
+                         int run, const int64_t* seg_offsets, int64_t seg_count,
+                         hipStream_t st) {
+    // without segments one workgroup per run; with them one per slot
+    const int64_t g = seg_offsets ? seg_count + N / run + 1 : (N + run - 1) / run;
+    if (g <= 0) return hipSuccess;
+    auto go = [&](auto kern, int threads) {
+        kern<<<(unsigned)g, threads, 0, st>>>(keys, pay, N, out, out_pay, seg_offsets, seg_count);
+    };
     switch (run) {
-        case 256: sort_runs_kernel<K, PAY, 256><<<(unsigned)g, run_threads<256>(), 0, st>>>(keys, pay, N, out, out_pay); break;
-        case 512: sort_runs_kernel<K, PAY, 512><<<(unsigned)g, run_threads<512>(), 0, st>>>(keys, pay, N, out, out_pay); break;
-        case 1024: sort_runs_kernel<K, PAY, 1024><<<(unsigned)g, run_threads<1024>(), 0, st>>>(keys, pay, N, out, out_pay); break;
-        case 2048: sort_runs_kernel<K, PAY, 2048><<<(unsigned)g, run_threads<2048>(), 0, st>>>(keys, pay, N, out, out_pay); break;
+        case 256: go(sort_runs_kernel<K, PAY, 256>, run_threads<256>()); break;
+        case 512: go(sort_runs_kernel<K, PAY, 512>, run_threads<512>()); break;
+        case 1024: go(sort_runs_kernel<K, PAY, 1024>, run_threads<1024>()); break;
+        case 2048: go(sort_runs_kernel<K, PAY, 2048>, run_threads<2048>()); break;
         case 4096:
             // 32-bit keys only: two buffers of 4096 keys and payloads fill 64 KiB
             if constexpr (sizeof(K) == 4) {
-                sort_runs_kernel<K, PAY, 4096><<<(unsigned)g, run_threads<4096>(), 0, st>>>(keys, pay, N, out, out_pay);
+                go(sort_runs_kernel<K, PAY, 4096>, run_threads<4096>());
                 break;
             } else {
                 return hipErrorInvalidValue;
@@ -151,11 +229,19 @@ int sort_passes(int64_t N, int run) {
     return p;
 }
 
-SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile) {
+SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile, int64_t seg_count,
+                       int64_t max_len) {
     SortLayout L;
     const size_t kb = (int)dtype_bytes(dtype);
-    L.passes = sort_passes(N, run);
-    L.count_max = N > run ? (N + 2 * (int64_t)run - 1) / (2 * (int64_t)run) : 1;
+    if (seg_count > 0) {
+        // passes until the longest segment is one run; the first pass has
+        // the most job slots
+        L.passes = sort_passes(max_len, run);
+        L.count_max = seg_count + N / (2 * (int64_t)run) + 1;
+    } else {
+        L.passes = sort_passes(N, run);
+        L.count_max = N > run ? (N + 2 * (int64_t)run - 1) / (2 * (int64_t)run) : 1;
+    }
     size_t off = 0;
     L.off_tmp_keys = off; off += align256((size_t)N * kb);
     L.off_tmp_pay = off; off += pay ? align256((size_t)N * 4) : 0;
@@ -170,7 +256,7 @@ SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile) {
 
 hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t N, void* out_keys,
                        uint32_t* out_pay, int run, int64_t tile, char* ws, const SortLayout& L,
-                       hipStream_t st) {
+                       hipStream_t st, const int64_t* seg_offsets, int64_t seg_count) {
     if (N <= 0) return hipSuccess;
     char* tmp_k = ws + L.off_tmp_keys;
     uint32_t* tmp_p = pay ? reinterpret_cast<uint32_t*>(ws + L.off_tmp_pay) : nullptr;
@@ -185,16 +271,24 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
     with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         e = pay ? launch_runs_t<K, true>(static_cast<const K*>(keys), pay, N,
-                                         reinterpret_cast<K*>(src_k), src_p, run, st)
+                                         reinterpret_cast<K*>(src_k), src_p, run, seg_offsets,
+                                         seg_count, st)
                 : launch_runs_t<K, false>(static_cast<const K*>(keys), nullptr, N,
-                                          reinterpret_cast<K*>(src_k), nullptr, run, st);
+                                          reinterpret_cast<K*>(src_k), nullptr, run, seg_offsets,
+                                          seg_count, st);
     });
     if (e != hipSuccess) return e;
-    for (int64_t w = run; w < N; w *= 2) {
-        const int64_t count = (N + 2 * w - 1) / (2 * w);
+    int64_t w = run;
+    for (int pass = 0; pass < L.passes; ++pass, w *= 2) {
+        // job slots of this pass: one per pair of runs, or (segments) the
+        // slot bound at width 2w
+        const int64_t count = seg_offsets ? seg_count + N / (2 * w) + 1 : (N + 2 * w - 1) / (2 * w);
         int64_t g = (count + 255) / 256;
         if (g > 4096) g = 4096;
-        sort_pass_jobs_kernel<<<(unsigned)g, 256, 0, st>>>(N, w, count, jobs);
+        if (seg_offsets)
+            seg_pass_jobs_kernel<<<(unsigned)g, 256, 0, st>>>(seg_offsets, seg_count, w, count, jobs);
+        else
+            sort_pass_jobs_kernel<<<(unsigned)g, 256, 0, st>>>(N, w, count, jobs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const BatchLayout BL = batch_layout(count, N, tile);
         e = launch_batch(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, tile,
@@ -204,6 +298,15 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
         uint32_t* tp = src_p; src_p = dst_p; dst_p = tp;
     }
     return hipSuccess;
+}
+
+hipError_t launch_seg_check(const int64_t* offsets, int64_t count, int64_t N, int64_t max_len,
+                            int* bad, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t g = (count + 255) / 256;
+    if (g > 4096) g = 4096;
+    seg_check_kernel<<<(unsigned)g, 256, 0, st>>>(offsets, count, N, max_len, bad);
+    return hipGetLastError();
 }
 
 }  // namespace sm

@@ -132,3 +132,26 @@ def test_learned_merge_error_paths(sm):
     q = sm._lib.stable_merge_learned_workspace_bytes
     assert q(100, 100, 0, 1, 0) == 0
     assert q(100, 100, 16, 1, 0) > 0 and q(100, 100, 16, 1, 1) >= q(100, 100, 16, 1, 0)
+
+
+def test_segmented_sort_error_paths(sm):
+    f = sm._lib.stable_merge_segmented_sort
+    o = sm.Options()
+
+    def call(keys=0x10000, pay=None, offs=0x50000, count=4, N=100, max_len=50, out=0x20000,
+             opay=None, dtype=1, ws=0x30000, ws_bytes=1 << 24):
+        return f(keys, pay, offs, count, N, max_len, out, opay, dtype, ws, ws_bytes,
+                 ctypes.byref(o), None)
+
+    assert call(dtype=6) == -2
+    assert call(count=0) == -1
+    assert call(max_len=101) == -1
+    assert call(max_len=-1) == -1
+    assert call(offs=None) == -1
+    assert call(pay=0x40000) == -1                                  # payload without out_payloads
+    assert call(out=0x10000 + 64) == -3                             # partial overlap
+    assert call(ws_bytes=8) == -4
+    assert call(N=0, max_len=0) == 0                                # nothing to do
+    q = sm._lib.stable_merge_segmented_sort_workspace_bytes
+    assert q(0, 100, 50, 1, 0, ctypes.byref(o)) == 0
+    assert q(4, 100, 50, 1, 0, ctypes.byref(o)) > 0

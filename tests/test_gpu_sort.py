@@ -134,3 +134,76 @@ def test_sort_float_total_order(dt):
     for run in (0, 2048):
         check_sort(keys, True, run=run)
         check_sort(keys, False, run=run)
+
+
+def oracle_segmented(keys, pay, offsets, run=512):
+    outk, outp = np.empty_like(keys), (None if pay is None else np.empty_like(pay))
+    for s in range(len(offsets) - 1):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        if hi > lo:
+            k, p = oracle.sort(keys[lo:hi], None if pay is None else pay[lo:hi], run)
+            outk[lo:hi] = k
+            if pay is not None:
+                outp[lo:hi] = p
+    return outk, outp
+
+
+def check_segmented(keys, lengths, with_pay=True, run=0, max_len=None, **kw):
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    N = int(offsets[-1])
+    assert N == len(keys)
+    pay = np.arange(N, dtype=np.uint32)[::-1].copy() if with_pay else None
+    rk, rp = oracle_segmented(keys, pay, offsets)
+    ml = max_len if max_len is not None else int(max(lengths) if len(lengths) else 0)
+    ck, cp = sm.segmented_sort(dev(keys), dev(offsets), ml, None if pay is None else dev(pay),
+                               run=run, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ck).view(np.uint8), rk.view(np.uint8)), "keys differ"
+    if with_pay:
+        assert np.array_equal(host(cp), rp), "payloads differ"
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_segmented_sort_mixed(dtype, with_pay):
+    """Segments of every size class at once: empty, one element, below,
+    at and above the run length, and long ones needing several passes."""
+    g = np.random.default_rng(41)
+    lengths = np.concatenate([[0, 1, 511, 512, 513, 0, 3000, 70_001, 2, 1024, 4097],
+                              g.integers(0, 2000, size=300), [0]])
+    keys = rand_keys(g, int(lengths.sum()), 97, dtype)
+    flush(f"segmented mixed dtype={np.dtype(dtype).name} pay={with_pay} count={len(lengths)}")
+    check_segmented(keys, lengths, with_pay)
+
+
+@pytest.mark.parametrize("run", [256, 2048])
+def test_segmented_sort_shapes(run):
+    """One segment (the plain sort); many tiny segments; a loose max_len
+    bound (extra passes that only copy); validation in the call; in place."""
+    g = np.random.default_rng(42)
+    N = 200_003
+    keys = rand_keys(g, N, 1000, np.uint32)
+    flush(f"segmented shapes run={run}")
+    check_segmented(keys, [N], True, run=run)
+    tiny = g.integers(0, 9, size=40_000)
+    check_segmented(rand_keys(g, int(tiny.sum()), 5, np.int32), tiny, True, run=run)
+    lens = g.integers(0, 5000, size=100)
+    k2 = rand_keys(g, int(lens.sum()), 50, np.uint64)
+    check_segmented(k2, lens, True, run=run, max_len=int(lens.sum()), validate=True)
+    offsets = dev(np.concatenate([[0], np.cumsum(lens)]).astype(np.int64))
+    dk = dev(k2)
+    sm.segmented_sort(dk, offsets, int(lens.max()), out_keys=dk, run=run)
+    torch.cuda.synchronize()
+    rk, _ = oracle_segmented(k2, None, host(offsets))
+    assert np.array_equal(host(dk), rk)
+
+
+def test_segmented_sort_validation():
+    keys = dev(np.arange(100, dtype=np.uint32)[::-1].copy())
+    bad = [np.array([0, 60, 40, 100]), np.array([0, 50, 99]), np.array([5, 50, 100])]
+    for offs in bad:
+        with pytest.raises(sm.SMError) as e:
+            sm.segmented_sort(keys, dev(offs.astype(np.int64)), 100, validate=True)
+        assert e.value.code == -1
+    with pytest.raises(sm.SMError):   # a segment longer than max_len
+        sm.segmented_sort(keys, dev(np.array([0, 70, 100], dtype=np.int64)), 50, validate=True)
