@@ -645,6 +645,48 @@ def bench_learned(args):
     outputs_equal = bool(torch.equal(out_p, out_l))
     fine_ms = _events_ms(lambda: merge_with(xl, yl, out_l), reps, stream)
     lw = windows[best_w]["ms"]
+    del out_p, ws
+
+    # the same models at the top-level split: blocks of 2368 (the tiled
+    # merge's block length), learned against plain partition, then the
+    # tiled merge
+    tile = 2368
+    tp_a, tp_b = (n + tile - 1) // tile, (m + tile - 1) // tile
+    txp = torch.empty(tp_a + 1, dtype=torch.int64, device=dev)
+    typ = torch.empty(tp_b + 1, dtype=torch.int64, device=dev)
+    txl, tyl = torch.empty_like(txp), torch.empty_like(typ)
+    tws = torch.empty(sm.pieces_workspace_bytes(n, m, tp_a, tp_b, torch.uint32),
+                      dtype=torch.uint8, device=dev)
+    W_top = int(best_w)
+
+    def top_plain():
+        sm.partition(keys, n, m, tp_a, tp_b, xbar=txp, ybar=typ, stream=stream)
+
+    def top_learned():
+        learned.partition_learned(keys, n, m, tp_a, tp_b, model_b, model_a, s0a, s0b, W_top,
+                                  xbar=txl, ybar=tyl, hist=hist, counters=cnt, stream=stream)
+
+    top_plain()
+    hist.zero_()
+    cnt.zero_()
+    top_learned()
+    torch.cuda.synchronize()
+    tc = cnt.cpu().numpy().astype(np.int64)
+    top_same = bool(torch.equal(txl, txp) and torch.equal(tyl, typ))
+    top_plain_ms = _events_ms(top_plain, reps, stream)
+    top_learned_ms = _events_ms(top_learned, reps, stream)
+    top_merge_ms = _events_ms(lambda: sm.merge_pieces(keys, n, m, tp_a, tp_b, txl, tyl,
+                                                      out_keys=out_l, workspace=tws,
+                                                      stream=stream), reps, stream)
+    top = {"block": tile, "splitters_per_side": tp_a, "ranks_equal_plain": top_same,
+           "plain_partition_ms": round(top_plain_ms, 4),
+           "learned_partition_ms": round(top_learned_ms, 4),
+           "probes_per_rank": round(tc[2] / max(tc[0], 1), 3),
+           "fallback_rate": round(tc[1] / max(tc[0], 1), 5),
+           "merge_ms": round(top_merge_ms, 4),
+           "end_to_end_Gelem/s": {
+               "plain": round((n + m) / ((top_plain_ms + top_merge_ms) * 1e-3) / 1e9, 2),
+               "learned": round((n + m) / ((top_learned_ms + top_merge_ms) * 1e-3) / 1e9, 2)}}
     return {"workload": "n=m=2^28 uint32, 3-component log-normal mixture (medians 2^10, 2^20, "
                         "2^28; sigma 0.5), sorted; block starts every 16 elements",
             "splitters_per_side": p_a, "train": {"samples": samples, "steps": steps,
@@ -658,7 +700,8 @@ def bench_learned(args):
             "partition_speedup_learned_vs_plain": round(plain_ms / lw, 3),
             "fine_merge_ms": round(fine_ms, 4), "outputs_bit_equal": outputs_equal,
             "end_to_end_Gelem/s": {"plain": round((n + m) / ((plain_ms + fine_ms) * 1e-3) / 1e9, 2),
-                                   "learned": round((n + m) / ((lw + fine_ms) * 1e-3) / 1e9, 2)}}
+                                   "learned": round((n + m) / ((lw + fine_ms) * 1e-3) / 1e9, 2)},
+            "top_level_split": top}
 
 
 if __name__ == "__main__":
