@@ -80,6 +80,12 @@ typedef enum {
  *  run        stable_merge_sort only: length of the runs sorted inside one
  *             workgroup before the merge passes; 256, 512, 1024, 2048, or
  *             4096 for 32-bit keys (0 = 512).
+ *  descending stable_merge, stable_merge_batched and the two sorts: nonzero
+ *             orders keys from largest to smallest (inputs non-increasing,
+ *             ties as in ascending order: A before B, input order within a
+ *             source).  The merges then need room for a copy of the keys in
+ *             the workspace (their workspace queries account for it when
+ *             the option is passed).
  *  reserved   must be zero.
  */
 typedef struct {
@@ -88,7 +94,8 @@ typedef struct {
     int32_t tile;
     int32_t validate;
     int32_t run;
-    int32_t reserved[5];
+    int32_t descending;
+    int32_t reserved[4];
 } sm_options;
 
 /* Message describing the last non-OK status returned on this thread. */

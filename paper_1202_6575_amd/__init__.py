@@ -53,7 +53,7 @@ class SMError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("p_a", ctypes.c_int64), ("p_b", ctypes.c_int64), ("tile", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("run", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("descending", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
@@ -112,14 +112,15 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(p_a=0, p_b=0, tile=0, validate=False, run=0) -> Options:
-    return Options(int(p_a), int(p_b), int(tile), int(bool(validate)), int(run))
+def _opts(p_a=0, p_b=0, tile=0, validate=False, run=0, descending=False) -> Options:
+    return Options(int(p_a), int(p_b), int(tile), int(bool(validate)), int(run),
+                   int(bool(descending)))
 
 
 def workspace_bytes(n: int, m: int, dtype: torch.dtype, has_payload: bool = False,
-                    p_a: int = 0, p_b: int = 0, tile: int = 0) -> int:
+                    p_a: int = 0, p_b: int = 0, tile: int = 0, descending: bool = False) -> int:
     """Device workspace bytes stable_merge needs (0 on bad arguments)."""
-    o = _opts(p_a, p_b, tile)
+    o = _opts(p_a, p_b, tile, descending=descending)
     return int(_lib.stable_merge_workspace_bytes(n, m, DTYPES[dtype], int(has_payload),
                                                  ctypes.byref(o)))
 
@@ -132,9 +133,10 @@ def pieces_workspace_bytes(n: int, m: int, p_a: int, p_b: int, dtype: torch.dtyp
 
 
 def batched_workspace_bytes(count: int, total: int, dtype: torch.dtype,
-                            has_payload: bool = False, tile: int = 0) -> int:
+                            has_payload: bool = False, tile: int = 0,
+                            descending: bool = False) -> int:
     """Device workspace bytes stable_merge_batched needs (0 on bad arguments)."""
-    o = _opts(0, 0, tile)
+    o = _opts(0, 0, tile, descending=descending)
     return int(_lib.stable_merge_batched_workspace_bytes(count, total, DTYPES[dtype],
                                                          int(has_payload), ctypes.byref(o)))
 
@@ -156,11 +158,12 @@ def _require_device(*ts):
 def merge(keys: torch.Tensor, n: int, m: int | None = None, payloads: torch.Tensor | None = None,
           *, out_keys: torch.Tensor | None = None, out_payloads: torch.Tensor | None = None,
           p_a: int = 0, p_b: int = 0, tile: int = 0, validate: bool = False,
-          workspace: torch.Tensor | None = None, stream=None):
+          descending: bool = False, workspace: torch.Tensor | None = None, stream=None):
     """Stable merge of A = keys[:n] and B = keys[n:n+m] (Section 2, Steps 1-4).
 
     Returns (out_keys, out_payloads); out_payloads is None without payloads.
-    Equal keys keep A before B; each source keeps its order."""
+    Equal keys keep A before B; each source keeps its order.  With
+    descending=True both inputs and the output run from largest to smallest."""
     if m is None:
         m = keys.numel() - n
     if keys.numel() < n + m:
@@ -171,7 +174,7 @@ def merge(keys: torch.Tensor, n: int, m: int | None = None, payloads: torch.Tens
         out_keys = torch.empty(n + m, dtype=keys.dtype, device=keys.device)
     if payloads is not None and out_payloads is None:
         out_payloads = torch.empty(n + m, dtype=torch.uint32, device=keys.device)
-    o = _opts(p_a, p_b, tile, validate)
+    o = _opts(p_a, p_b, tile, validate, descending=descending)
     need = int(_lib.stable_merge_workspace_bytes(n, m, code, int(payloads is not None),
                                                  ctypes.byref(o)))
     if workspace is None:
@@ -223,7 +226,8 @@ def merge_pieces(keys: torch.Tensor, n: int, m: int, p_a: int, p_b: int, xbar: t
 def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
                   payloads: torch.Tensor | None = None, *, out_keys: torch.Tensor | None = None,
                   out_payloads: torch.Tensor | None = None, tile: int = 0,
-                  validate: bool = False, workspace: torch.Tensor | None = None, stream=None):
+                  validate: bool = False, descending: bool = False,
+                  workspace: torch.Tensor | None = None, stream=None):
     """Independent stable merges of many pairs in one launch sequence.
 
     Pair k is keys[offsets[k]:offsets[k+1]] with its first n_a[k] elements as
@@ -241,7 +245,7 @@ def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
         out_keys = torch.empty_like(keys)
     if payloads is not None and out_payloads is None:
         out_payloads = torch.empty(total, dtype=torch.uint32, device=keys.device)
-    o = _opts(0, 0, tile, validate)
+    o = _opts(0, 0, tile, validate, descending=descending)
     if workspace is None:
         need = int(_lib.stable_merge_batched_workspace_bytes(count, total, code,
                                                              int(payloads is not None),
@@ -256,9 +260,11 @@ def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
 
 def sort(keys: torch.Tensor, payloads: torch.Tensor | None = None, *,
          out_keys: torch.Tensor | None = None, out_payloads: torch.Tensor | None = None,
-         run: int = 0, tile: int = 0, workspace: torch.Tensor | None = None, stream=None):
-    """Stable merge sort of keys (payloads travel along).  Passing the inputs
-    as out_keys / out_payloads sorts in place.  Returns (out_keys, out_payloads)."""
+         run: int = 0, tile: int = 0, descending: bool = False,
+         workspace: torch.Tensor | None = None, stream=None):
+    """Stable merge sort of keys (payloads travel along), smallest first or,
+    with descending=True, largest first.  Passing the inputs as out_keys /
+    out_payloads sorts in place.  Returns (out_keys, out_payloads)."""
     _require_device(keys, payloads, out_keys, out_payloads, workspace)
     N = keys.numel()
     code = _dtype_code(keys)
@@ -266,7 +272,7 @@ def sort(keys: torch.Tensor, payloads: torch.Tensor | None = None, *,
         out_keys = torch.empty_like(keys)
     if payloads is not None and out_payloads is None:
         out_payloads = torch.empty(N, dtype=torch.uint32, device=keys.device)
-    o = _opts(0, 0, tile, False, run)
+    o = _opts(0, 0, tile, False, run, descending)
     if workspace is None:
         need = int(_lib.stable_merge_sort_workspace_bytes(N, code, int(payloads is not None),
                                                           ctypes.byref(o)))
@@ -288,7 +294,8 @@ def segmented_sort_workspace_bytes(count: int, N: int, max_len: int, dtype: torc
 def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, max_len: int,
                    payloads: torch.Tensor | None = None, *, out_keys: torch.Tensor | None = None,
                    out_payloads: torch.Tensor | None = None, run: int = 0, tile: int = 0,
-                   validate: bool = False, workspace: torch.Tensor | None = None, stream=None):
+                   validate: bool = False, descending: bool = False,
+                   workspace: torch.Tensor | None = None, stream=None):
     """Stable sort of every segment keys[offsets[s]:offsets[s+1]] on its own.
     offsets is a device int64 tensor of count + 1 entries from 0 to N; max_len
     bounds the segment lengths (host value).  Returns (out_keys, out_payloads)."""
@@ -302,7 +309,7 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, max_len: int,
         out_keys = torch.empty_like(keys)
     if payloads is not None and out_payloads is None:
         out_payloads = torch.empty(N, dtype=torch.uint32, device=keys.device)
-    o = _opts(0, 0, tile, validate, run)
+    o = _opts(0, 0, tile, validate, run, descending)
     if workspace is None:
         need = int(_lib.stable_merge_segmented_sort_workspace_bytes(
             count, N, max_len, code, int(payloads is not None), ctypes.byref(o)))

@@ -196,8 +196,8 @@ const char* sm_last_error(void) { return g_err; }
 
 int sm_version(void) { return 200; }
 
-size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
-                                    const sm_options* opt) {
+static size_t stable_merge_workspace_bytes_asc(int64_t n, int64_t m, int dtype, int has_payload,
+                                               const sm_options* opt) {
     Plan pl;
     if (!dtype_ok(dtype)) return 0;
     const bool pay = has_payload != 0;
@@ -251,9 +251,9 @@ int stable_merge_pieces(const void* keys, const uint32_t* payloads, int64_t n, i
                            static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
-int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t m, void* out_keys,
-                 uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                 const sm_options* opt, void* stream) {
+static int stable_merge_asc(const void* keys, const uint32_t* payloads, int64_t n, int64_t m,
+                            void* out_keys, uint32_t* out_payloads, int dtype, void* ws,
+                            size_t ws_bytes, const sm_options* opt, void* stream) {
     const bool pay = payloads != nullptr;
     Plan pl;
     int rc = make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
@@ -290,8 +290,8 @@ int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t 
                            w + pl.off_desc, st);
 }
 
-size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
-                                            int has_payload, const sm_options* opt) {
+static size_t stable_merge_batched_workspace_bytes_asc(int64_t count, int64_t total, int dtype,
+                                                       int has_payload, const sm_options* opt) {
     if (!dtype_ok(dtype) || count < 0 || total < 0 || total > (1ll << 40)) return 0;
     const bool pay = has_payload != 0;
     const int32_t tile = pick_tile(dtype, pay, opt);
@@ -300,10 +300,11 @@ size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dt
     return align256((size_t)count * sm::kPieceDescBytes) + L.bytes;
 }
 
-int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64_t* offsets,
-                         const int64_t* n_a, int64_t count, int64_t total, void* out_keys,
-                         uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                         const sm_options* opt, void* stream) {
+static int stable_merge_batched_asc(const void* keys, const uint32_t* payloads,
+                                    const int64_t* offsets, const int64_t* n_a, int64_t count,
+                                    int64_t total, void* out_keys, uint32_t* out_payloads,
+                                    int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
+                                    void* stream) {
     if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
     if (count < 0 || total < 0 || total > (1ll << 40))
         return fail(SM_ERR_ARG, "count and total must be >= 0 (count=%lld, total=%lld)",
@@ -412,9 +413,9 @@ size_t seg_flag_offset(const sm::SortLayout& L) { return align256(L.bytes); }
 
 }  // namespace
 
-int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
-                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                      const sm_options* opt, void* stream) {
+static int stable_merge_sort_asc(const void* keys, const uint32_t* payloads, int64_t N,
+                                 void* out_keys, uint32_t* out_payloads, int dtype, void* ws,
+                                 size_t ws_bytes, const sm_options* opt, void* stream) {
     const bool pay = payloads != nullptr;
     int run;
     int32_t tile;
@@ -445,11 +446,12 @@ size_t stable_merge_segmented_sort_workspace_bytes(int64_t count, int64_t N, int
     return seg_flag_offset(L) + 256;
 }
 
-int stable_merge_segmented_sort(const void* keys, const uint32_t* payloads,
-                                const int64_t* offsets, int64_t count, int64_t N,
-                                int64_t max_len, void* out_keys, uint32_t* out_payloads,
-                                int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
-                                void* stream) {
+static int stable_merge_segmented_sort_asc(const void* keys, const uint32_t* payloads,
+                                           const int64_t* offsets, int64_t count, int64_t N,
+                                           int64_t max_len, void* out_keys,
+                                           uint32_t* out_payloads, int dtype, void* ws,
+                                           size_t ws_bytes, const sm_options* opt,
+                                           void* stream) {
     const bool pay = payloads != nullptr;
     if (count < 1) return fail(SM_ERR_ARG, "count must be >= 1");
     if (count > (1ll << 31)) return fail(SM_ERR_ARG, "count must be below 2^31");
@@ -484,6 +486,157 @@ int stable_merge_segmented_sort(const void* keys, const uint32_t* payloads,
                                    static_cast<char*>(ws), L, st, offsets, count);
     if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
     return SM_OK;
+}
+
+// ---- descending order ------------------------------------------------------
+// A descending stable merge or sort is the ascending one of keys whose order
+// has been reversed by an involution (bitwise NOT, or a float's sign bit),
+// transformed back: equal keys stay equal, so the tie rules are unchanged.
+// The merges read the transformed keys from a copy in the workspace (the
+// inputs are the caller's); the sorts transform into their output and sort
+// it in place.
+
+static bool descending(const sm_options* opt) { return opt && opt->descending; }
+
+static sm_options ascending_copy(const sm_options* opt) {
+    sm_options o = *opt;
+    o.descending = 0;
+    return o;
+}
+
+size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
+                                    const sm_options* opt) {
+    const size_t base = stable_merge_workspace_bytes_asc(n, m, dtype, has_payload, opt);
+    if (base == 0 || !descending(opt)) return base;
+    return align256(base) + align256((size_t)(n + m) * key_bytes(dtype));
+}
+
+int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t m, void* out_keys,
+                 uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                 const sm_options* opt, void* stream) {
+    if (!descending(opt))
+        return stable_merge_asc(keys, payloads, n, m, out_keys, out_payloads, dtype, ws, ws_bytes,
+                                opt, stream);
+    int rc = check_sizes(n, m, dtype);
+    if (rc != SM_OK) return rc;
+    const size_t base = stable_merge_workspace_bytes_asc(n, m, dtype, payloads != nullptr, opt);
+    if (base == 0) return fail(SM_ERR_ARG, "unsupported sizes or options");
+    if (n + m == 0) return SM_OK;
+    rc = check_buffers(keys, payloads, n + m, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    rc = check_ws(ws, ws_bytes, stable_merge_workspace_bytes(n, m, dtype, payloads != nullptr, opt));
+    if (rc != SM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* flipped = static_cast<char*>(ws) + align256(base);
+    hipError_t e = sm::launch_flip_order(dtype, keys, flipped, n + m, st);
+    if (e != hipSuccess) return hip_fail(e, "order flip");
+    const sm_options o = ascending_copy(opt);
+    rc = stable_merge_asc(flipped, payloads, n, m, out_keys, out_payloads, dtype, ws,
+                          align256(base), &o, stream);
+    if (rc != SM_OK) return rc;
+    e = sm::launch_flip_order(dtype, out_keys, out_keys, n + m, st);
+    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
+}
+
+size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
+                                            int has_payload, const sm_options* opt) {
+    const size_t base = stable_merge_batched_workspace_bytes_asc(count, total, dtype, has_payload,
+                                                                 opt);
+    if (base == 0 || !descending(opt)) return base;
+    return align256(base) + align256((size_t)total * key_bytes(dtype));
+}
+
+int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64_t* offsets,
+                         const int64_t* n_a, int64_t count, int64_t total, void* out_keys,
+                         uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                         const sm_options* opt, void* stream) {
+    if (!descending(opt))
+        return stable_merge_batched_asc(keys, payloads, offsets, n_a, count, total, out_keys,
+                                        out_payloads, dtype, ws, ws_bytes, opt, stream);
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    const size_t base = stable_merge_batched_workspace_bytes_asc(count, total, dtype,
+                                                                 payloads != nullptr, opt);
+    if (base == 0) return fail(SM_ERR_ARG, "unsupported sizes or options");
+    if (count == 0 || total == 0) return SM_OK;
+    int rc = check_buffers(keys, payloads, total, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    rc = check_ws(ws, ws_bytes,
+                  stable_merge_batched_workspace_bytes(count, total, dtype, payloads != nullptr,
+                                                       opt));
+    if (rc != SM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* flipped = static_cast<char*>(ws) + align256(base);
+    hipError_t e = sm::launch_flip_order(dtype, keys, flipped, total, st);
+    if (e != hipSuccess) return hip_fail(e, "order flip");
+    const sm_options o = ascending_copy(opt);
+    rc = stable_merge_batched_asc(flipped, payloads, offsets, n_a, count, total, out_keys,
+                                  out_payloads, dtype, ws, align256(base), &o, stream);
+    if (rc != SM_OK) return rc;
+    e = sm::launch_flip_order(dtype, out_keys, out_keys, total, st);
+    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
+}
+
+int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                      const sm_options* opt, void* stream) {
+    if (!descending(opt))
+        return stable_merge_sort_asc(keys, payloads, N, out_keys, out_payloads, dtype, ws,
+                                     ws_bytes, opt, stream);
+    int run;
+    int32_t tile;
+    sm::SortLayout L;
+    int rc = sort_plan(N, dtype, payloads != nullptr, opt, &run, &tile, &L);
+    if (rc != SM_OK) return rc;
+    if ((payloads == nullptr) != (out_payloads == nullptr))
+        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
+    if (N == 0) return SM_OK;
+    rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
+                            L.bytes);
+    if (rc != SM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = sm::launch_flip_order(dtype, keys, out_keys, N, st);
+    if (e != hipSuccess) return hip_fail(e, "order flip");
+    const sm_options o = ascending_copy(opt);
+    rc = stable_merge_sort_asc(out_keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
+                               &o, stream);
+    if (rc != SM_OK) return rc;
+    e = sm::launch_flip_order(dtype, out_keys, out_keys, N, st);
+    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
+}
+
+int stable_merge_segmented_sort(const void* keys, const uint32_t* payloads,
+                                const int64_t* offsets, int64_t count, int64_t N,
+                                int64_t max_len, void* out_keys, uint32_t* out_payloads,
+                                int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
+                                void* stream) {
+    if (!descending(opt))
+        return stable_merge_segmented_sort_asc(keys, payloads, offsets, count, N, max_len,
+                                               out_keys, out_payloads, dtype, ws, ws_bytes, opt,
+                                               stream);
+    if (count < 1 || count > (1ll << 31)) return fail(SM_ERR_ARG, "1 <= count < 2^31 required");
+    if (max_len < 0 || max_len > N) return fail(SM_ERR_ARG, "0 <= max_len <= N required");
+    int run;
+    int32_t tile;
+    sm::SortLayout L;
+    int rc = sort_plan(N, dtype, payloads != nullptr, opt, &run, &tile, &L, count, max_len);
+    if (rc != SM_OK) return rc;
+    if ((payloads == nullptr) != (out_payloads == nullptr))
+        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
+    if (!offsets) return fail(SM_ERR_ARG, "offsets must not be NULL");
+    if (N == 0) return SM_OK;
+    rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
+                            seg_flag_offset(L) + 256);
+    if (rc != SM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = sm::launch_flip_order(dtype, keys, out_keys, N, st);
+    if (e != hipSuccess) return hip_fail(e, "order flip");
+    const sm_options o = ascending_copy(opt);
+    rc = stable_merge_segmented_sort_asc(out_keys, payloads, offsets, count, N, max_len,
+                                         out_keys, out_payloads, dtype, ws, ws_bytes, &o,
+                                         stream);
+    if (rc != SM_OK) return rc;
+    e = sm::launch_flip_order(dtype, out_keys, out_keys, N, st);
+    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
 }
 
 size_t sm_mlp_grad_workspace_bytes(int64_t samples) {

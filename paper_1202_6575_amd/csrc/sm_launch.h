@@ -57,4 +57,8 @@ constexpr size_t kPieceDescBytes = 32;
 hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, int* flag,
                            hipStream_t st);
 
+// dst = src with every key's order reversed (descending order), N keys of
+// type dtype; src == dst allowed; both 16-byte aligned.
+hipError_t launch_flip_order(int dtype, const void* src, void* dst, int64_t N, hipStream_t st);
+
 }  // namespace sm
