@@ -123,9 +123,10 @@ def main():
     ap.add_argument("--check", action="store_true", help="compare one output with the oracle")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, sort and learned measurements")
-    ap.add_argument("--extras", default="heavy_ties,skewed,batched,batched_literal,sort,learned",
+    ap.add_argument("--extras",
+                    default="heavy_ties,skewed,batched,batched_literal,sort,learned,descending",
                     help="comma-separated subset of heavy_ties, skewed, batched, "
-                         "batched_literal, sort, learned")
+                         "batched_literal, sort, learned, descending")
     ap.add_argument("--sort-run", type=int, default=512, help="run length of the merge sort")
     ap.add_argument("--batch-log2max", type=int, default=15,
                     help="batched pairs: totals log-uniform in [16, 2^this]")
@@ -284,6 +285,10 @@ def main():
         if "learned" in extras:
             res["learned"] = bench_learned(args)
             log(f"bench: learned {json.dumps(res['learned'])}")
+            torch.cuda.empty_cache()
+        if "descending" in extras:
+            res["descending"] = bench_descending(args)
+            log(f"bench: descending {json.dumps(res['descending'])}")
     print(json.dumps(res), flush=True)
 
 
@@ -510,6 +515,41 @@ def bench_skewed(args):
                                  "p99": int(torch.quantile(sz, 0.99)),
                                  "log2_histogram": {f"[{(1 << k) - 1},{(1 << (k + 1)) - 1})": v
                                                     for k, v in enumerate(hist) if v}}}
+
+
+def bench_descending(args):
+    """The whole stable_merge call on the large plain merge's shape, ascending
+    and descending (the same keys reversed): the cost of the two extra
+    passes of the order transform."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_1202_6575_amd as sm
+
+    n = m = 1 << args.log2n
+    log(f"bench: descending, n=m=2^{args.log2n} uint32")
+    A, B = datagen.uniform_pair(n, m, 0, 2 ** 32, np.uint32, seed=datagen.BASE_SEED + 1)
+    dev = torch.device("cuda:0")
+    asc = torch.from_numpy(np.concatenate([A, B])).to(dev)
+    desc = torch.from_numpy(np.concatenate([A[::-1], B[::-1]])).to(dev)
+    del A, B
+    out = torch.empty_like(asc)
+    ws = torch.empty(sm.workspace_bytes(n, m, torch.uint32, descending=True), dtype=torch.uint8,
+                     device=dev)
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"stable_merge of n=m=2^{args.log2n} uint32 uniform keys, keys only, "
+                       f"default tile; descending input is the ascending one reversed"}
+    for name, keys, flag in (("ascending", asc, False), ("descending", desc, True)):
+        def run():
+            sm.merge(keys, n, m, out_keys=out, descending=flag, workspace=ws, stream=stream)
+        run()
+        ms = _events_ms(run, max(args.steps // 2, 3), stream)
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_Gelem/s"] = round((n + m) / (ms * 1e-3) / 1e9, 2)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    res["output_non_increasing"] = bool((o[1:] <= o[:-1]).all())
+    return res
 
 
 def bench_sort(args):
