@@ -83,9 +83,8 @@ typedef enum {
  *  descending stable_merge, stable_merge_batched and the two sorts: nonzero
  *             orders keys from largest to smallest (inputs non-increasing,
  *             ties as in ascending order: A before B, input order within a
- *             source).  The merges then need room for a copy of the keys in
- *             the workspace (their workspace queries account for it when
- *             the option is passed).
+ *             source).  Same workspace, same speed: the kernels are
+ *             compiled for both orders.
  *  reserved   must be zero.
  */
 typedef struct {

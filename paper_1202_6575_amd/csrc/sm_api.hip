@@ -41,6 +41,11 @@ size_t key_bytes(int dtype) { return sm::dtype_bytes(dtype); }
 
 bool dtype_ok(int dtype) { return sm::dtype_known(dtype); }
 
+// The kernel dtype code: the public code plus the requested order.
+int kernel_dtype(int dtype, const sm_options* opt) {
+    return sm::kernel_dtype(dtype, opt && opt->descending);
+}
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -163,14 +168,15 @@ int check_ws(const void* ws, size_t ws_bytes, size_t need) {
 }
 
 // Steps 3-4 and the merges, once Steps 1-2 have written xbar / ybar.
-// `tail` is the workspace from the descriptors on.
+// `tail` is the workspace from the descriptors on; dtype is a kernel code.
 int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t* payloads,
                     int64_t n, int64_t m, const int64_t* xbar, const int64_t* ybar,
                     void* out_keys, uint32_t* out_payloads, char* tail, hipStream_t st) {
     sm::PieceDesc* desc = reinterpret_cast<sm::PieceDesc*>(tail);
     const int64_t P = pl.p_a + pl.p_b;
     hipError_t e;
-    if (!pl.hier && pl.cap <= sm::kFineCap) {
+    // the small-block merge has an ascending form only
+    if (!pl.hier && pl.cap <= sm::kFineCap && !(dtype & sm::kDescending)) {
         e = sm::launch_fine_merge(dtype, keys, payloads, n, m, pl.p_a, pl.p_b, xbar, ybar, out_keys,
                                   out_payloads, st);
         if (e != hipSuccess) return hip_fail(e, "merge launch");
@@ -196,8 +202,8 @@ const char* sm_last_error(void) { return g_err; }
 
 int sm_version(void) { return 200; }
 
-static size_t stable_merge_workspace_bytes_asc(int64_t n, int64_t m, int dtype, int has_payload,
-                                               const sm_options* opt) {
+size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
+                                    const sm_options* opt) {
     Plan pl;
     if (!dtype_ok(dtype)) return 0;
     const bool pay = has_payload != 0;
@@ -251,9 +257,9 @@ int stable_merge_pieces(const void* keys, const uint32_t* payloads, int64_t n, i
                            static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
-static int stable_merge_asc(const void* keys, const uint32_t* payloads, int64_t n, int64_t m,
-                            void* out_keys, uint32_t* out_payloads, int dtype, void* ws,
-                            size_t ws_bytes, const sm_options* opt, void* stream) {
+int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t m, void* out_keys,
+                 uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                 const sm_options* opt, void* stream) {
     const bool pay = payloads != nullptr;
     Plan pl;
     int rc = make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
@@ -273,25 +279,26 @@ static int stable_merge_asc(const void* keys, const uint32_t* payloads, int64_t 
     int* flag = reinterpret_cast<int*>(w + pl.off_flag);
     hipError_t e;
 
+    const int kd = kernel_dtype(dtype, opt);
     if (opt && opt->validate) {
         int host_flag = 0;
         e = sm::launch_clear(flag, 1, st);
-        if (e == hipSuccess) e = sm::launch_validate(dtype, keys, n, m, flag, st);
+        if (e == hipSuccess) e = sm::launch_validate(kd, keys, n, m, flag, st);
         if (e != hipSuccess) return hip_fail(e, "validate launch");
         e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "validate readback");
-        if (host_flag) return fail(SM_ERR_UNSORTED, "A or B is not non-decreasing");
+        if (host_flag) return fail(SM_ERR_UNSORTED, "A or B is not sorted in the requested order");
     }
 
-    e = sm::launch_partition(dtype, keys, n, m, pl.p_a, pl.p_b, xbar, ybar, st);
+    e = sm::launch_partition(kd, keys, n, m, pl.p_a, pl.p_b, xbar, ybar, st);
     if (e != hipSuccess) return hip_fail(e, "partition launch");
-    return cases_and_merge(pl, dtype, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
+    return cases_and_merge(pl, kd, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
                            w + pl.off_desc, st);
 }
 
-static size_t stable_merge_batched_workspace_bytes_asc(int64_t count, int64_t total, int dtype,
-                                                       int has_payload, const sm_options* opt) {
+size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
+                                            int has_payload, const sm_options* opt) {
     if (!dtype_ok(dtype) || count < 0 || total < 0 || total > (1ll << 40)) return 0;
     const bool pay = has_payload != 0;
     const int32_t tile = pick_tile(dtype, pay, opt);
@@ -300,11 +307,10 @@ static size_t stable_merge_batched_workspace_bytes_asc(int64_t count, int64_t to
     return align256((size_t)count * sm::kPieceDescBytes) + L.bytes;
 }
 
-static int stable_merge_batched_asc(const void* keys, const uint32_t* payloads,
-                                    const int64_t* offsets, const int64_t* n_a, int64_t count,
-                                    int64_t total, void* out_keys, uint32_t* out_payloads,
-                                    int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
-                                    void* stream) {
+int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64_t* offsets,
+                         const int64_t* n_a, int64_t count, int64_t total, void* out_keys,
+                         uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                         const sm_options* opt, void* stream) {
     if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
     if (count < 0 || total < 0 || total > (1ll << 40))
         return fail(SM_ERR_ARG, "count and total must be >= 0 (count=%lld, total=%lld)",
@@ -338,14 +344,16 @@ static int stable_merge_batched_asc(const void* keys, const uint32_t* payloads,
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "validate readback");
         if (host_flag) return fail(SM_ERR_ARG, "offsets / n_a describe an invalid pair");
-        e = sm::launch_batch_validate(dtype, keys, offsets, n_a, count, total, flag, st);
+        e = sm::launch_batch_validate(kernel_dtype(dtype, opt), keys, offsets, n_a, count, total,
+                                      flag, st);
         if (e == hipSuccess) e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "validate readback");
-        if (host_flag) return fail(SM_ERR_UNSORTED, "an A or B of the batch is not non-decreasing");
+        if (host_flag)
+            return fail(SM_ERR_UNSORTED, "an A or B of the batch is not sorted in the requested order");
     }
-    e = sm::launch_batch(dtype, keys, payloads, total, out_keys, out_payloads, total, jobs, count,
-                         tile, w + off_eng, L, st);
+    e = sm::launch_batch(kernel_dtype(dtype, opt), keys, payloads, total, out_keys, out_payloads,
+                         total, jobs, count, tile, w + off_eng, L, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return SM_OK;
 }
@@ -413,9 +421,9 @@ size_t seg_flag_offset(const sm::SortLayout& L) { return align256(L.bytes); }
 
 }  // namespace
 
-static int stable_merge_sort_asc(const void* keys, const uint32_t* payloads, int64_t N,
-                                 void* out_keys, uint32_t* out_payloads, int dtype, void* ws,
-                                 size_t ws_bytes, const sm_options* opt, void* stream) {
+int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                      const sm_options* opt, void* stream) {
     const bool pay = payloads != nullptr;
     int run;
     int32_t tile;
@@ -428,8 +436,9 @@ static int stable_merge_sort_asc(const void* keys, const uint32_t* payloads, int
     rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
                             L.bytes);
     if (rc != SM_OK) return rc;
-    hipError_t e = sm::launch_sort(dtype, keys, payloads, N, out_keys, out_payloads, run, tile,
-                                   static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
+    hipError_t e = sm::launch_sort(kernel_dtype(dtype, opt), keys, payloads, N, out_keys,
+                                   out_payloads, run, tile, static_cast<char*>(ws), L,
+                                   static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "sort launch");
     return SM_OK;
 }
@@ -446,12 +455,11 @@ size_t stable_merge_segmented_sort_workspace_bytes(int64_t count, int64_t N, int
     return seg_flag_offset(L) + 256;
 }
 
-static int stable_merge_segmented_sort_asc(const void* keys, const uint32_t* payloads,
-                                           const int64_t* offsets, int64_t count, int64_t N,
-                                           int64_t max_len, void* out_keys,
-                                           uint32_t* out_payloads, int dtype, void* ws,
-                                           size_t ws_bytes, const sm_options* opt,
-                                           void* stream) {
+int stable_merge_segmented_sort(const void* keys, const uint32_t* payloads,
+                                const int64_t* offsets, int64_t count, int64_t N,
+                                int64_t max_len, void* out_keys, uint32_t* out_payloads,
+                                int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
+                                void* stream) {
     const bool pay = payloads != nullptr;
     if (count < 1) return fail(SM_ERR_ARG, "count must be >= 1");
     if (count > (1ll << 31)) return fail(SM_ERR_ARG, "count must be below 2^31");
@@ -482,161 +490,11 @@ static int stable_merge_segmented_sort_asc(const void* keys, const uint32_t* pay
             return fail(SM_ERR_ARG, "offsets must run from 0 to N without decreasing, with no "
                                     "segment longer than max_len");
     }
-    hipError_t e = sm::launch_sort(dtype, keys, payloads, N, out_keys, out_payloads, run, tile,
-                                   static_cast<char*>(ws), L, st, offsets, count);
+    hipError_t e = sm::launch_sort(kernel_dtype(dtype, opt), keys, payloads, N, out_keys,
+                                   out_payloads, run, tile, static_cast<char*>(ws), L, st, offsets,
+                                   count);
     if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
     return SM_OK;
-}
-
-// ---- descending order ------------------------------------------------------
-// A descending stable merge or sort is the ascending one of keys whose order
-// has been reversed by an involution (bitwise NOT, or a float's sign bit),
-// transformed back: equal keys stay equal, so the tie rules are unchanged.
-// The merges read the transformed keys from a copy in the workspace (the
-// inputs are the caller's); the sorts transform into their output and sort
-// it in place.
-
-static bool descending(const sm_options* opt) { return opt && opt->descending; }
-
-static sm_options ascending_copy(const sm_options* opt) {
-    sm_options o = *opt;
-    o.descending = 0;
-    return o;
-}
-
-size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
-                                    const sm_options* opt) {
-    const size_t base = stable_merge_workspace_bytes_asc(n, m, dtype, has_payload, opt);
-    if (base == 0 || !descending(opt)) return base;
-    return align256(base) + align256((size_t)(n + m) * key_bytes(dtype));
-}
-
-int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t m, void* out_keys,
-                 uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                 const sm_options* opt, void* stream) {
-    if (!descending(opt))
-        return stable_merge_asc(keys, payloads, n, m, out_keys, out_payloads, dtype, ws, ws_bytes,
-                                opt, stream);
-    int rc = check_sizes(n, m, dtype);
-    if (rc != SM_OK) return rc;
-    const size_t base = stable_merge_workspace_bytes_asc(n, m, dtype, payloads != nullptr, opt);
-    if (base == 0) return fail(SM_ERR_ARG, "unsupported sizes or options");
-    if (n + m == 0) return SM_OK;
-    rc = check_buffers(keys, payloads, n + m, out_keys, out_payloads, dtype);
-    if (rc != SM_OK) return rc;
-    rc = check_ws(ws, ws_bytes, stable_merge_workspace_bytes(n, m, dtype, payloads != nullptr, opt));
-    if (rc != SM_OK) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    char* flipped = static_cast<char*>(ws) + align256(base);
-    hipError_t e = sm::launch_flip_order(dtype, keys, flipped, n + m, st);
-    if (e != hipSuccess) return hip_fail(e, "order flip");
-    const sm_options o = ascending_copy(opt);
-    rc = stable_merge_asc(flipped, payloads, n, m, out_keys, out_payloads, dtype, ws,
-                          align256(base), &o, stream);
-    if (rc != SM_OK) return rc;
-    e = sm::launch_flip_order(dtype, out_keys, out_keys, n + m, st);
-    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
-}
-
-size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
-                                            int has_payload, const sm_options* opt) {
-    const size_t base = stable_merge_batched_workspace_bytes_asc(count, total, dtype, has_payload,
-                                                                 opt);
-    if (base == 0 || !descending(opt)) return base;
-    return align256(base) + align256((size_t)total * key_bytes(dtype));
-}
-
-int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64_t* offsets,
-                         const int64_t* n_a, int64_t count, int64_t total, void* out_keys,
-                         uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                         const sm_options* opt, void* stream) {
-    if (!descending(opt))
-        return stable_merge_batched_asc(keys, payloads, offsets, n_a, count, total, out_keys,
-                                        out_payloads, dtype, ws, ws_bytes, opt, stream);
-    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
-    const size_t base = stable_merge_batched_workspace_bytes_asc(count, total, dtype,
-                                                                 payloads != nullptr, opt);
-    if (base == 0) return fail(SM_ERR_ARG, "unsupported sizes or options");
-    if (count == 0 || total == 0) return SM_OK;
-    int rc = check_buffers(keys, payloads, total, out_keys, out_payloads, dtype);
-    if (rc != SM_OK) return rc;
-    rc = check_ws(ws, ws_bytes,
-                  stable_merge_batched_workspace_bytes(count, total, dtype, payloads != nullptr,
-                                                       opt));
-    if (rc != SM_OK) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    char* flipped = static_cast<char*>(ws) + align256(base);
-    hipError_t e = sm::launch_flip_order(dtype, keys, flipped, total, st);
-    if (e != hipSuccess) return hip_fail(e, "order flip");
-    const sm_options o = ascending_copy(opt);
-    rc = stable_merge_batched_asc(flipped, payloads, offsets, n_a, count, total, out_keys,
-                                  out_payloads, dtype, ws, align256(base), &o, stream);
-    if (rc != SM_OK) return rc;
-    e = sm::launch_flip_order(dtype, out_keys, out_keys, total, st);
-    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
-}
-
-int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
-                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                      const sm_options* opt, void* stream) {
-    if (!descending(opt))
-        return stable_merge_sort_asc(keys, payloads, N, out_keys, out_payloads, dtype, ws,
-                                     ws_bytes, opt, stream);
-    int run;
-    int32_t tile;
-    sm::SortLayout L;
-    int rc = sort_plan(N, dtype, payloads != nullptr, opt, &run, &tile, &L);
-    if (rc != SM_OK) return rc;
-    if ((payloads == nullptr) != (out_payloads == nullptr))
-        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
-    if (N == 0) return SM_OK;
-    rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
-                            L.bytes);
-    if (rc != SM_OK) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = sm::launch_flip_order(dtype, keys, out_keys, N, st);
-    if (e != hipSuccess) return hip_fail(e, "order flip");
-    const sm_options o = ascending_copy(opt);
-    rc = stable_merge_sort_asc(out_keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
-                               &o, stream);
-    if (rc != SM_OK) return rc;
-    e = sm::launch_flip_order(dtype, out_keys, out_keys, N, st);
-    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
-}
-
-int stable_merge_segmented_sort(const void* keys, const uint32_t* payloads,
-                                const int64_t* offsets, int64_t count, int64_t N,
-                                int64_t max_len, void* out_keys, uint32_t* out_payloads,
-                                int dtype, void* ws, size_t ws_bytes, const sm_options* opt,
-                                void* stream) {
-    if (!descending(opt))
-        return stable_merge_segmented_sort_asc(keys, payloads, offsets, count, N, max_len,
-                                               out_keys, out_payloads, dtype, ws, ws_bytes, opt,
-                                               stream);
-    if (count < 1 || count > (1ll << 31)) return fail(SM_ERR_ARG, "1 <= count < 2^31 required");
-    if (max_len < 0 || max_len > N) return fail(SM_ERR_ARG, "0 <= max_len <= N required");
-    int run;
-    int32_t tile;
-    sm::SortLayout L;
-    int rc = sort_plan(N, dtype, payloads != nullptr, opt, &run, &tile, &L, count, max_len);
-    if (rc != SM_OK) return rc;
-    if ((payloads == nullptr) != (out_payloads == nullptr))
-        return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
-    if (!offsets) return fail(SM_ERR_ARG, "offsets must not be NULL");
-    if (N == 0) return SM_OK;
-    rc = check_sort_buffers(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes,
-                            seg_flag_offset(L) + 256);
-    if (rc != SM_OK) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = sm::launch_flip_order(dtype, keys, out_keys, N, st);
-    if (e != hipSuccess) return hip_fail(e, "order flip");
-    const sm_options o = ascending_copy(opt);
-    rc = stable_merge_segmented_sort_asc(out_keys, payloads, offsets, count, N, max_len,
-                                         out_keys, out_payloads, dtype, ws, ws_bytes, &o,
-                                         stream);
-    if (rc != SM_OK) return rc;
-    e = sm::launch_flip_order(dtype, out_keys, out_keys, N, st);
-    return e == hipSuccess ? SM_OK : hip_fail(e, "order flip");
 }
 
 size_t sm_mlp_grad_workspace_bytes(int64_t samples) {

@@ -6,6 +6,10 @@
 
 namespace sm {
 
+// Every `dtype` below is a kernel dtype code (sm_keys.h): a public key type
+// code, with kDescending set for descending order where a launcher supports
+// it (the small-block merge and the learned kernels do not).
+
 // Workgroup size of the merge kernels: p = 256 lane-level processing elements.
 constexpr int kMergeThreads = 256;
 // Largest dynamic LDS a merge workgroup may use (gfx950: 160 KiB per CU).
@@ -53,12 +57,9 @@ int device_cu_count();
 constexpr size_t kPieceDescBytes = 32;
 
 // Sets *flag (device int) to 1 if keys[0, n) or keys[n, n + m) is not
-// non-decreasing; *flag must be 0 before the launch.
+// sorted in the order of the kernel dtype code; *flag must be 0 before the
+// launch.
 hipError_t launch_validate(int dtype, const void* keys, int64_t n, int64_t m, int* flag,
                            hipStream_t st);
-
-// dst = src with every key's order reversed (descending order), N keys of
-// type dtype; src == dst allowed; both 16-byte aligned.
-hipError_t launch_flip_order(int dtype, const void* src, void* dst, int64_t N, hipStream_t st);
 
 }  // namespace sm

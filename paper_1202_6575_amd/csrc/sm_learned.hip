@@ -445,7 +445,7 @@ hipError_t launch_mlp_grad(int dtype, const float* P, const void* keys, const fl
     const int64_t blocks = mlp_grad_blocks(S);
     const int64_t per_block = (S + blocks - 1) / blocks;
     float* partial = static_cast<float*>(ws);
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         mlp_grad_kernel<K><<<(unsigned)blocks, kGradThreads, 0, st>>>(
             P, static_cast<const K*>(keys), target, S, per_block > 0 ? per_block : 1, partial);
@@ -466,7 +466,7 @@ hipError_t launch_mlp_adam(float* P, float* M, float* V, const float* G, int64_t
 
 hipError_t launch_mlp_init(int dtype, const void* sorted_keys, const float* target, int64_t S,
                            float* P, hipStream_t st) {
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         mlp_init_kernel<K><<<1, 64, 0, st>>>(static_cast<const K*>(sorted_keys), target, S, P);
     });
@@ -476,7 +476,7 @@ hipError_t launch_mlp_init(int dtype, const void* sorted_keys, const float* targ
 hipError_t launch_mlp_predict(int dtype, const float* P, const void* keys, int64_t q, int64_t len,
                               int64_t* rhat, hipStream_t st) {
     if (q <= 0) return hipSuccess;
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         mlp_predict_kernel<K><<<grid_for(q, 8192), 256, 0, st>>>(P, static_cast<const K*>(keys), q,
                                                                   len, rhat);
@@ -488,7 +488,7 @@ hipError_t launch_rank_search(int dtype, const void* X, int64_t len, const void*
                               int is_high, const int64_t* guess, int64_t step0, int64_t window,
                               int64_t* ranks, int32_t* probes, int32_t* fallback, hipStream_t st) {
     if (q <= 0) return hipSuccess;
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         rank_search_kernel<K><<<grid_for(q, 8192), 256, 0, st>>>(
             static_cast<const K*>(X), len, static_cast<const K*>(queries), q, is_high, guess, step0,
@@ -508,7 +508,7 @@ hipError_t launch_learned_partition(int dtype, const void* keys, int64_t n, int6
     // spends the time on the per-workgroup counter atomics (measured 1.26,
     // 1.19 and 1.75 ms)
     const unsigned grid = grid_for(p_a + p_b + 2, (int64_t)device_cu_count() * 64);
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         learned_partition_kernel<K><<<grid, 256, 0, st>>>(
             static_cast<const K*>(keys), n, m, p_a, p_b, model_b, model_a, step0_a, step0_b, window,
@@ -542,7 +542,7 @@ hipError_t launch_rank_model_train(int dtype, const void* X, int64_t len, const 
     float* grad = reinterpret_cast<float*>(ws + L.off_grad);
     float* M = reinterpret_cast<float*>(ws + L.off_m);
     float* V = reinterpret_cast<float*>(ws + L.off_v);
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         rank_sample_kernel<K><<<grid_for(S, 4096), 256, 0, st>>>(
             static_cast<const K*>(X), len, static_cast<const K*>(Q), q_len, is_high, S, seed,

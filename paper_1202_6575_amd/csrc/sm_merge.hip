@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void validate_kernel(const K* __restrict__ key
 
 uint32_t merge_lds_bytes(int dtype, bool pay, uint32_t cap) {
     uint32_t r = 0;
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         r = pay ? MergeSmem<K, true, kMergeThreads>::bytes(cap)
                 : MergeSmem<K, false, kMergeThreads>::bytes(cap);
@@ -633,6 +633,7 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
                             const int64_t* ybar, void* out_keys, uint32_t* out_pay,
                             hipStream_t st) {
     if (p_a + p_b <= 0 || n + m <= 0) return hipSuccess;
+    if (dtype & kDescending) return hipErrorInvalidValue;  // ascending order only
     const unsigned grid = (unsigned)((p_a + kFineG - 1) / kFineG);
     // staging capacity: the workgroup's A blocks in full, and twice that (at
     // least 2048) of B, within 64 KiB of LDS (B shrinks first; if A alone
@@ -648,7 +649,7 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
     if (FineSmem(capA, capB).bytes_for(esz) > kFineLds) capA = capB = 0;
     const FineSmem fs(capA, capB);
     hipError_t e = hipSuccess;
-    with_key_type(dtype, [&](auto z) {
+    with_key_type_asc(dtype, [&](auto z) {
         using K = decltype(z);
         const uint32_t lds = fs.bytes_for(esz);
         if (pay) {
