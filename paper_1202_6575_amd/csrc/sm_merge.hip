@@ -65,10 +65,13 @@ __global__ __launch_bounds__(256) void cases_kernel(int64_t n, int64_t m, int64_
     desc[w] = d;
 }
 
-// Persistent merge: workgroup g merges subproblems [g*P/G, (g+1)*P/G) in order.
-// While it merges subproblem w, the 16-byte loads of subproblem w+1 are in
-// flight in registers (R chunks per thread) and the stores of subproblem w-1
-// are draining.
+// Persistent merge: workgroup g of G merges subproblems g, g + G, g + 2G, ...
+// (interleaved: at any moment the grid works on neighbouring subproblems,
+// so it sweeps the arrays front to back, and a workgroup's share is a
+// sample of the whole list rather than one stretch of it, which evens out
+// lists of uneven subproblems).  While it merges subproblem w, the 16-byte
+// loads of its next subproblem are in flight in registers (R chunks per
+// thread) and the stores of its previous one are draining.
 template <typename K, bool PAY, int L, int R>
 __global__ __launch_bounds__(L) void merge_persistent_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
@@ -83,22 +86,21 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
         P = pd < P ? (pd > 0 ? pd : 0) : P;
     }
     const int64_t G = gridDim.x;
-    const int64_t w0 = (int64_t)blockIdx.x * P / G;
-    const int64_t w1 = ((int64_t)blockIdx.x + 1) * P / G;
-    if (w0 >= w1) return;
+    const int64_t w0 = blockIdx.x;
+    if (w0 >= P) return;
     u32x4 rk[R], rp[R];
     PieceDesc d = desc[w0];
     if (!desc_ok(d, nkeys, nout, cap)) d.a_f = d.b_f = 0;
     SegPlan cur = make_plan<K, PAY>(d);
     SegPlan prev = cur;
     prefetch<K, PAY, L, R>(cur, keys, (uint64_t)nkeys, pay, rk, rp);
-    for (int64_t w = w0; w < w1; ++w) {
-        const bool more = w + 1 < w1;
+    for (int64_t w = w0; w < P; w += G) {
+        const bool more = w + G < P;
         PieceDesc dn;
         dn.ka0 = dn.kb0 = dn.out0 = 0;
         dn.a_f = dn.b_f = 0;
         if (more) {
-            dn = desc[w + 1];
+            dn = desc[w + G];
             if (!desc_ok(dn, nkeys, nout, cap)) dn.a_f = dn.b_f = 0;
         }
         const SegPlan nxt = make_plan<K, PAY>(dn);
@@ -123,10 +125,10 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
 }
 
 // The same with two subproblems in flight: while the workgroup merges
-// subproblem w, the loads of w + 1 and w + 2 are in flight in two register
-// sets, so every load has two merges' time to land.  Per step: wait for the
-// oldest set, commit it to LDS, write back w - 1, issue the loads of w + 2
-// into the freed set, merge w.  The write-back precedes the loads, so at the
+// subproblem w, the loads of w + G and w + 2G (its next two) are in flight
+// in two register sets, so every load has two merges' time to land.  Per
+// step: wait for the oldest set, commit it to LDS, write back w - G, issue
+// the loads of w + 2G into the freed set, merge w.  The write-back precedes the loads, so at the
 // next wait the operations younger than the awaited loads are one
 // write-back and then the other set's loads: waiting until no more than that
 // set's load count is in flight leaves at most that set in flight.
@@ -142,8 +144,8 @@ __device__ __forceinline__ void merge_pipelined(
         P = pd < P ? (pd > 0 ? pd : 0) : P;
     }
     const int64_t G = gridDim.x;
-    const int64_t w0 = (int64_t)blockIdx.x * P / G;
-    const int64_t w1 = ((int64_t)blockIdx.x + 1) * P / G;
+    const int64_t w0 = blockIdx.x;
+    const int64_t w1 = P;
     if (w0 >= w1) return;
     auto plan_of = [&](int64_t w) {
         PieceDesc d;
@@ -157,7 +159,7 @@ __device__ __forceinline__ void merge_pipelined(
     };
     u32x4 rkA[R], rpA[R], rkB[R], rpB[R];
     SegPlan cur = plan_of(w0);
-    SegPlan nxt = plan_of(w0 + 1);
+    SegPlan nxt = plan_of(w0 + G);
     SegPlan prev = cur;
     // Every step issues its loads, also for a subproblem past the range (an
     // empty one, whose few loads are never used): the awaited set is then
@@ -170,7 +172,7 @@ __device__ __forceinline__ void merge_pipelined(
     prefetch_whole<K, PAY, L, R>(cur, rkeys, rpay, rkA, rpA);
     prefetch_whole<K, PAY, L, R>(nxt, rkeys, rpay, rkB, rpB);
     auto step = [&](u32x4 (&rk)[R], u32x4 (&rp)[R], int64_t w) {
-        const SegPlan nn = plan_of(w + 2);
+        const SegPlan nn = plan_of(w + 2 * G);
         wait_vm<PAY ? 2 * R : R>();
         commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
         __syncthreads();
@@ -186,9 +188,9 @@ __device__ __forceinline__ void merge_pipelined(
     // pairs of steps, then a lone last step: no path through the loop runs a
     // set's step twice in a row (its loads would then be the youngest)
     int64_t w = w0;
-    for (; w + 1 < w1; w += 2) {
+    for (; w + G < w1; w += 2 * G) {
         step(rkA, rpA, w);
-        step(rkB, rpB, w + 1);
+        step(rkB, rpB, w + G);
     }
     if (w < w1) step(rkA, rpA, w);
     write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
