@@ -73,6 +73,23 @@ def test_merge_descending_inputs_untouched_and_tiles():
         sm.merge(dev(asc), len(A), len(B), descending=True, validate=True)
 
 
+@pytest.mark.parametrize("dtype", [np.int32, np.uint64, np.float32])
+def test_merge_descending_small_blocks(dtype):
+    """Blocks of a few elements: ascending merges take the small-block
+    kernel there, descending ones the general merge kernel."""
+    g = np.random.default_rng(58)
+    for n, m, p in [(10_000, 10_000, 2000), (3001, 7, 1000), (64, 640, 64)]:
+        A, B = desc_sorted(g, n, 30, dtype), desc_sorted(g, m, 30, dtype)
+        keys = np.concatenate([A, B])
+        flush(f"merge descending small blocks {np.dtype(dtype).name} n={n} m={m} p={p}")
+        ck, cp = sm.merge(dev(keys), n, m, dev(np.arange(n + m, dtype=np.uint32)),
+                          p_a=p, p_b=p, descending=True)
+        torch.cuda.synchronize()
+        perm = stable_desc_perm(keys)
+        assert same_bits(host(ck), keys[perm])
+        assert np.array_equal(host(cp), perm.astype(np.uint32))
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_batched_descending(dtype):
     g = np.random.default_rng(53)
