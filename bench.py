@@ -555,6 +555,7 @@ def bench_descending(args):
 def bench_sort(args):
     """Stable merge sort of 2^28 (uint32 key uniform in [0, 2^24), uint32
     index) pairs: runs of 512 formed in LDS, then 19 merge passes."""
+    import numpy as np
     import torch
     import datagen
     import datagen.torch_gen as tg
@@ -583,11 +584,45 @@ def bench_sort(args):
         passes += 1
     # run formation + every pass read and write 8 bytes per element
     alg = N * 8 * 2 * (passes + 1)
-    return {"workload": f"N=2^28 uint32 keys uniform in [0, 2^24), uint32 payload = index, "
-                        f"runs of {run_len}, {passes} merge passes",
-            "Gelem/s": round(N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3),
-            "passes": passes, "output_sorted": sorted_ok,
-            "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1)}
+    res = {"workload": f"N=2^28 uint32 keys uniform in [0, 2^24), uint32 payload = index, "
+                       f"runs of {run_len}, {passes} merge passes",
+           "Gelem/s": round(N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3),
+           "passes": passes, "output_sorted": sorted_ok,
+           "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1)}
+    # the same sort with learned cross ranks in every pass: one model of the
+    # keys' distribution, trained on the first 2^20 keys
+    from paper_1202_6575_amd import learned
+    log("bench: learned merge sort")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model, frac = learned.train_sort_model(keys, sample=1 << 20, samples=1 << 18, steps=1000)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3
+    lk, lp = torch.empty_like(keys), torch.empty_like(pay)
+    cnt = torch.zeros(2, dtype=torch.uint64, device=keys.device)
+    zero = torch.zeros(learned.NPARAM, dtype=torch.float32, device=keys.device)
+    cz = torch.zeros(2, dtype=torch.uint64, device=keys.device)
+
+    def run_learned():
+        learned.sort_learned(keys, model, frac, pay, out_keys=lk, out_payloads=lp, run=run_len,
+                             counters=cnt, workspace=ws, stream=stream)
+
+    run_learned()
+    learned.sort_learned(keys, zero, 1.0, pay, out_keys=lk, out_payloads=lp, run=run_len,
+                         counters=cz, workspace=ws, stream=stream)
+    run_learned()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(lk, ok) and torch.equal(lp, op))
+    c = cnt.cpu().numpy().astype(np.int64) // 2
+    z = cz.cpu().numpy().astype(np.int64)
+    lms = _events_ms(run_learned, 3, stream)
+    res["learned"] = {"train_ms": round(train_ms, 1), "step_frac": float(frac),
+                      "ms": round(lms, 3), "plain_ms": round(ms, 3),
+                      "outputs_bit_equal": same,
+                      "searches_per_sort": int(c[0]),
+                      "probes_per_rank": round(float(c[1]) / max(int(c[0]), 1), 2),
+                      "uninformed_probes_per_rank": round(float(z[1]) / max(int(z[0]), 1), 2)}
+    return res
 
 
 def _bin_label(k: int) -> str:

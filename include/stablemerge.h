@@ -371,6 +371,28 @@ SM_API int stable_merge_learned(const void *keys, const uint32_t *payloads, int6
 SM_API size_t stable_merge_learned_workspace_bytes(int64_t n, int64_t m, int64_t block, int dtype,
                                                    int has_payload);
 
+/*
+ * stable_merge_sort with learned cross ranks in every merge pass (an
+ * addition to the paper; the learned partition of stable_merge_learned,
+ * amortised over the passes).  The runs of every pass are drawn from the
+ * same keys, so one model serves them all: `model` (97 device floats, the
+ * layout of sm_mlp_grad) maps a key to its normalised rank in a sorted
+ * sample of the keys.  A cross rank in a run of len elements is searched
+ * from the guess model(key) * len, stepping away by the largest power of
+ * two <= max(1, step_frac * len) and doubling before the bisection, so
+ * step_frac is the model's relative rank error (0 <= step_frac <= 1).
+ * The output is byte for byte that of stable_merge_sort whatever the model
+ * predicts; only the number of probes changes.  counters (device, may be
+ * NULL) accumulate [searches, probes] over all passes.  Ascending order
+ * only (opt->descending is rejected); workspace and other arguments as
+ * stable_merge_sort (stable_merge_sort_workspace_bytes).
+ */
+SM_API int stable_merge_sort_learned(const void *keys, const uint32_t *payloads, int64_t N,
+                                     void *out_keys, uint32_t *out_payloads, int dtype,
+                                     const float *model, float step_frac, uint64_t *counters,
+                                     void *ws, size_t ws_bytes, const sm_options *opt,
+                                     void *stream);
+
 #ifdef __cplusplus
 }
 #endif

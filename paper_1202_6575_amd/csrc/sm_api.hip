@@ -421,9 +421,9 @@ size_t seg_flag_offset(const sm::SortLayout& L) { return align256(L.bytes); }
 
 }  // namespace
 
-int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
-                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
-                      const sm_options* opt, void* stream) {
+static int sort_impl(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                     uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                     const sm_options* opt, void* stream, const sm::LearnedSearch* ls) {
     const bool pay = payloads != nullptr;
     int run;
     int32_t tile;
@@ -438,9 +438,32 @@ int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, voi
     if (rc != SM_OK) return rc;
     hipError_t e = sm::launch_sort(kernel_dtype(dtype, opt), keys, payloads, N, out_keys,
                                    out_payloads, run, tile, static_cast<char*>(ws), L,
-                                   static_cast<hipStream_t>(stream));
+                                   static_cast<hipStream_t>(stream), nullptr, 0, ls);
     if (e != hipSuccess) return hip_fail(e, "sort launch");
     return SM_OK;
+}
+
+int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                      uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
+                      const sm_options* opt, void* stream) {
+    return sort_impl(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes, opt, stream,
+                     nullptr);
+}
+
+int stable_merge_sort_learned(const void* keys, const uint32_t* payloads, int64_t N,
+                              void* out_keys, uint32_t* out_payloads, int dtype,
+                              const float* model, float step_frac, uint64_t* counters, void* ws,
+                              size_t ws_bytes, const sm_options* opt, void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (!model) return fail(SM_ERR_ARG, "model must not be NULL");
+    if (!(step_frac >= 0.0f && step_frac <= 1.0f))
+        return fail(SM_ERR_ARG, "step_frac must be in [0, 1]");
+    if (opt && opt->descending)
+        return fail(SM_ERR_ARG, "the learned sort is ascending only");
+    const sm::LearnedSearch ls{model, step_frac,
+                               reinterpret_cast<unsigned long long*>(counters)};
+    return sort_impl(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes, opt, stream,
+                     &ls);
 }
 
 size_t stable_merge_segmented_sort_workspace_bytes(int64_t count, int64_t N, int64_t max_len,

@@ -33,10 +33,23 @@ hipError_t launch_batch_validate(int dtype, const void* keys, const int64_t* off
 // Zero n device ints with a kernel (graph-capture safe).
 hipError_t launch_clear(int* p, int n, hipStream_t st);
 
-// plan + scan, partition, cases and merge for `count` jobs.
+// Cross ranks from a learned starting point (ascending key types only):
+// `model` (97 device floats) maps a key to its normalised rank in any
+// sorted array drawn from the keys' distribution; the search for the rank
+// of x in an array of len elements starts at model(x) * len and steps away
+// by the largest power of two <= max(1, step_frac * len), doubling, before
+// bisecting.  counters (device, may be null) accumulate [searches, probes].
+struct LearnedSearch {
+    const float* model;
+    float step_frac;
+    unsigned long long* counters;
+};
+
+// plan + scan, partition, cases and merge for `count` jobs; with `ls` the
+// partition searches start at learned guesses (the ranks are the same).
 hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
                         void* out_keys, uint32_t* out_pay, int64_t nout, const PieceDesc* jobs,
                         int64_t count, int64_t tile, char* ws, const BatchLayout& L,
-                        hipStream_t st);
+                        hipStream_t st, const LearnedSearch* ls = nullptr);
 
 }  // namespace sm

@@ -19,6 +19,7 @@
 #include "sm_device.h"
 #include "sm_launch.h"
 #include "sm_batch.h"
+#include "sm_learned_dev.h"
 
 namespace sm {
 
@@ -161,15 +162,39 @@ __device__ __forceinline__ int64_t owner(const int64_t* start, int64_t count, in
     return lo;
 }
 
+// Rank of x in X[0, len) (rank_high if HIGH) by bounded search from the
+// model's guess; adds the probes to `probes`.
+template <bool HIGH, typename K>
+__device__ __forceinline__ int64_t learned_rank(const K* X, int64_t len, K x, const float* model,
+                                                float step_frac, unsigned long long& probes) {
+    if constexpr (IsDesc<K>::value) {
+        return HIGH ? rank_high<K, int64_t>(X, len, x) : rank_low<K, int64_t>(X, len, x);
+    } else {
+        const int64_t g = predict(model, feature(x), len);
+        const float s = step_frac * (float)len;
+        const int64_t step0 = s >= 2.0f ? (int64_t)1 << (int)floorf(log2f(s)) : 1;
+        int np;
+        bool fb;
+        // a window of 2 len never ends the walk early: a step of len or more
+        // from any guess already leaves the array
+        const int64_t r = bounded_search<K, HIGH>(X, len, x, g, step0, 2 * len + 2, np, fb);
+        probes += (unsigned long long)np;
+        return r;
+    }
+}
+
 // Steps 1-2 for every split job: flat cross-rank index s -> (job, block).
+// With `model` the searches start at learned guesses (same ranks).
 template <typename K>
 __global__ __launch_bounds__(256) void batch_partition_kernel(
     const K* __restrict__ keys, const PieceDesc* __restrict__ jobs, int64_t count, int64_t tile,
     uint32_t cap, const int64_t* __restrict__ sstart, const int64_t* __restrict__ totals,
-    int64_t s_max, int64_t* __restrict__ ranks) {
+    int64_t s_max, int64_t* __restrict__ ranks, const float* __restrict__ model, float step_frac,
+    unsigned long long* __restrict__ counters) {
     // the counts bound S by s_max; the clamp only keeps a corrupted job list
     // inside the workspace
     const int64_t S = min(totals[1], s_max);
+    unsigned long long n_search = 0, n_probe = 0;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S;
          s += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = owner(sstart, count, s);
@@ -183,13 +208,32 @@ __global__ __launch_bounds__(256) void batch_partition_kernel(
         int64_t r;
         if (u <= p_a) {
             const int64_t xu = Blocks<int64_t>(a, p_a).start(u);
-            r = xu < a ? rank_low<K, int64_t>(B, b, A[xu]) : b;
+            if (xu >= a) r = b;
+            else if (model) {
+                r = learned_rank<false, K>(B, b, A[xu], model, step_frac, n_probe);
+                ++n_search;
+            } else r = rank_low<K, int64_t>(B, b, A[xu]);
         } else {
             const int64_t v = u - (p_a + 1);
             const int64_t yv = Blocks<int64_t>(b, p_b).start(v);
-            r = yv < b ? rank_high<K, int64_t>(A, a, B[yv]) : a;
+            if (yv >= b) r = a;
+            else if (model) {
+                r = learned_rank<true, K>(A, a, B[yv], model, step_frac, n_probe);
+                ++n_search;
+            } else r = rank_high<K, int64_t>(A, a, B[yv]);
         }
         ranks[s] = r;
+    }
+    if (counters) {
+        // summed per wave, one atomic per wave and counter
+        for (int o = 32; o > 0; o >>= 1) {
+            n_search += __shfl_xor(n_search, o);
+            n_probe += __shfl_xor(n_probe, o);
+        }
+        if ((threadIdx.x & 63) == 0 && n_search) {
+            atomicAdd(&counters[0], n_search);
+            atomicAdd(&counters[1], n_probe);
+        }
     }
 }
 
@@ -345,8 +389,9 @@ hipError_t launch_clear(int* p, int n, hipStream_t st) {
 hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
                         void* out_keys, uint32_t* out_pay, int64_t nout, const PieceDesc* jobs,
                         int64_t count, int64_t tile, char* ws, const BatchLayout& L,
-                        hipStream_t st) {
+                        hipStream_t st, const LearnedSearch* ls) {
     if (count <= 0) return hipSuccess;
+    if (ls && (dtype & kDescending)) return hipErrorInvalidValue;  // ascending models only
     const uint32_t cap = merge_cap_for_tile((int32_t)tile);
     int64_t* pstart = reinterpret_cast<int64_t*>(ws + L.off_pstart);
     int64_t* sstart = reinterpret_cast<int64_t*>(ws + L.off_sstart);
@@ -372,9 +417,9 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
     if (gs > grid) gs = grid;
     with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
-        batch_partition_kernel<K><<<(unsigned)gs, 256, 0, st>>>(static_cast<const K*>(keys), jobs,
-                                                                count, tile, cap, sstart, totals,
-                                                                L.s_max, ranks);
+        batch_partition_kernel<K><<<(unsigned)gs, 256, 0, st>>>(
+            static_cast<const K*>(keys), jobs, count, tile, cap, sstart, totals, L.s_max, ranks,
+            ls ? ls->model : nullptr, ls ? ls->step_frac : 0.0f, ls ? ls->counters : nullptr);
     });
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int64_t gp = (L.p_max + 255) / 256;

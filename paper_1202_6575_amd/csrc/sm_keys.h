@@ -83,6 +83,14 @@ template <typename K>
 struct KeyMax<Desc<K>> {
     static constexpr Desc<K> v = {KeyMin<K>::v};
 };
+template <typename K>
+struct IsDesc {
+    static constexpr bool value = false;
+};
+template <typename K>
+struct IsDesc<Desc<K>> {
+    static constexpr bool value = true;
+};
 
 // Public dtype codes, and the kernel codes that add the order.
 constexpr int kDescending = 8;

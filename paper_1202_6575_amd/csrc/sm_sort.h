@@ -34,10 +34,11 @@ SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile,
 // With seg_offsets (device, seg_count + 1 entries from 0 to N) every
 // segment is sorted on its own: runs start at segment starts and every merge
 // pass pairs runs within a segment.
+// With `ls` every merge pass finds its cross ranks from learned guesses.
 hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t N, void* out_keys,
                        uint32_t* out_pay, int run, int64_t tile, char* ws, const SortLayout& L,
                        hipStream_t st, const int64_t* seg_offsets = nullptr,
-                       int64_t seg_count = 0);
+                       int64_t seg_count = 0, const LearnedSearch* ls = nullptr);
 
 // Sets *bad (device int, cleared beforehand) unless the offsets run from 0
 // to N without decreasing and no segment is longer than max_len.

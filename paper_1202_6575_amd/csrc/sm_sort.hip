@@ -256,7 +256,8 @@ SortLayout sort_layout(int64_t N, int dtype, bool pay, int run, int64_t tile, in
 
 hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t N, void* out_keys,
                        uint32_t* out_pay, int run, int64_t tile, char* ws, const SortLayout& L,
-                       hipStream_t st, const int64_t* seg_offsets, int64_t seg_count) {
+                       hipStream_t st, const int64_t* seg_offsets, int64_t seg_count,
+                       const LearnedSearch* ls) {
     if (N <= 0) return hipSuccess;
     char* tmp_k = ws + L.off_tmp_keys;
     uint32_t* tmp_p = pay ? reinterpret_cast<uint32_t*>(ws + L.off_tmp_pay) : nullptr;
@@ -292,7 +293,7 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const BatchLayout BL = batch_layout(count, N, tile);
         e = launch_batch(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, tile,
-                         ws + L.off_batch, BL, st);
+                         ws + L.off_batch, BL, st, ls);
         if (e != hipSuccess) return e;
         char* tk = src_k; src_k = dst_k; dst_k = tk;
         uint32_t* tp = src_p; src_p = dst_p; dst_p = tp;

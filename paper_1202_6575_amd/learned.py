@@ -35,6 +35,9 @@ _lib.sm_mlp_predict.restype = _i32
 _lib.sm_mlp_predict.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp]
 _lib.sm_rank_model_workspace_bytes.restype = _sz
 _lib.sm_rank_model_workspace_bytes.argtypes = [_i64, _i32]
+_lib.stable_merge_sort_learned.restype = _i32
+_lib.stable_merge_sort_learned.argtypes = [_vp, _vp, _i64, _vp, _vp, _i32, _vp, _f32, _vp, _vp,
+                                           _sz, _vp, _vp]
 _lib.sm_rank_model_train.restype = _i32
 _lib.sm_rank_model_train.argtypes = [_vp, _i64, _vp, _i64, _i32, _i32, _i64, _i64, _f32, _u64,
                                      _vp, _vp, _vp, _sz, _vp]
@@ -191,3 +194,51 @@ def merge_learned(keys, n, m, model_b, model_a, step0_a=1, step0_b=1, block=16, 
                                      _ptr(hist), _ptr(counters), _ptr(workspace),
                                      workspace.numel(), _stream_ptr(stream)))
     return out_keys, out_payloads, hist, counters
+
+
+def train_sort_model(keys, sample=1 << 20, samples=1 << 18, steps=1000, lr=3e-3, seed=0, *,
+                     stream=None):
+    """A model of the keys' distribution for sort_learned: the first `sample`
+    keys, sorted by the library's own sort, are the modelled array (an
+    unbiased sample when the input order carries no information; any model
+    gives the same sort).  Returns (params, step_frac) with step_frac the
+    RMS rank error relative to the array length."""
+    from . import sort as _sort
+    _require_device(keys)
+    k = min(int(sample), keys.numel())
+    if k < 2:
+        raise SMError(-1, "train_sort_model: need at least two keys")
+    X, _ = _sort(keys[:k].contiguous(), stream=stream)
+    params, loss = train_rank_model(X, X, False, samples=min(int(samples), k), steps=steps, lr=lr,
+                                    seed=seed, stream=stream)
+    return params, math.sqrt(max(float(loss.item()), 0.0))
+
+
+def sort_learned(keys, model, step_frac, payloads=None, *, out_keys=None, out_payloads=None,
+                 run: int = 0, tile: int = 0, counters=None, workspace=None, stream=None):
+    """stable_merge_sort with learned cross ranks in every merge pass.
+    Returns (out_keys, out_payloads, counters) with counters = [searches,
+    probes] accumulated over the passes; the output equals sort()'s."""
+    from . import _opts
+    _f32_params(model)
+    _require_device(keys, payloads, out_keys, out_payloads, counters, workspace)
+    N = keys.numel()
+    code = _dtype_code(keys)
+    dev = keys.device
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(N, dtype=torch.uint32, device=dev)
+    if counters is None:
+        counters = torch.zeros(2, dtype=torch.uint64, device=dev)
+    o = _opts(0, 0, tile, False, run)
+    if workspace is None:
+        need = int(_lib.stable_merge_sort_workspace_bytes(N, code, int(payloads is not None),
+                                                          ctypes.byref(o)))
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=dev)
+    _check(_lib.stable_merge_sort_learned(_ptr(keys), _ptr(payloads), N, _ptr(out_keys),
+                                          _ptr(out_payloads), code, _ptr(model),
+                                          float(step_frac), _ptr(counters), _ptr(workspace),
+                                          workspace.numel(), ctypes.byref(o),
+                                          _stream_ptr(stream)))
+    return out_keys, out_payloads, counters

@@ -174,3 +174,25 @@ def test_descending_workspace_and_errors(sm):
     assert call_merge(sm, dtype=8, opts=o) == -2      # kernel-only codes are not public
     assert call_merge(sm, dtype=9) == -2
     assert call_merge(sm, n=0, m=0, opts=o) == 0
+
+
+def test_sort_learned_error_paths(sm):
+    f = sm._lib.stable_merge_sort_learned
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_float,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                  ctypes.c_void_p]
+
+    def call(model=0x50000, step=0.01, dtype=1, N=100, opts=None, ws_bytes=1 << 24):
+        o = opts if opts is not None else sm.Options()
+        return f(0x10000, None, N, 0x20000, None, dtype, model, step, None, 0x30000, ws_bytes,
+                 ctypes.byref(o), None)
+
+    assert call(model=None) == -1
+    assert call(dtype=7) == -2
+    assert call(step=-1.0) == -1
+    assert call(step=float("nan")) == -1
+    assert call(opts=sm._opts(descending=True)) == -1
+    assert call(ws_bytes=8) == -4
+    assert call(N=0) == 0
