@@ -85,7 +85,8 @@ typedef enum {
  *             ties as in ascending order: A before B, input order within a
  *             source).  Same workspace, same speed: the kernels are
  *             compiled for both orders.
- *  reserved   must be zero.
+ *  reserved   must be zero: calls reject anything else with SM_ERR_ARG and
+ *             the workspace queries return 0.
  */
 typedef struct {
     int64_t p_a;

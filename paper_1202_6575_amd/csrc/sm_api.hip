@@ -41,6 +41,14 @@ size_t key_bytes(int dtype) { return sm::dtype_bytes(dtype); }
 
 bool dtype_ok(int dtype) { return sm::dtype_known(dtype); }
 
+// sm_options.reserved must be zero (room for later options).
+bool options_ok(const sm_options* opt) {
+    if (!opt) return true;
+    for (int32_t r : opt->reserved)
+        if (r != 0) return false;
+    return true;
+}
+
 // The kernel dtype code: the public code plus the requested order.
 int kernel_dtype(int dtype, const sm_options* opt) {
     return sm::kernel_dtype(dtype, opt && opt->descending);
@@ -205,7 +213,7 @@ int sm_version(void) { return 200; }
 size_t stable_merge_workspace_bytes(int64_t n, int64_t m, int dtype, int has_payload,
                                     const sm_options* opt) {
     Plan pl;
-    if (!dtype_ok(dtype)) return 0;
+    if (!dtype_ok(dtype) || !options_ok(opt)) return 0;
     const bool pay = has_payload != 0;
     if (make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
                   pick_tile(dtype, pay, opt), &pl) != SM_OK)
@@ -261,6 +269,7 @@ int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t 
                  uint32_t* out_payloads, int dtype, void* ws, size_t ws_bytes,
                  const sm_options* opt, void* stream) {
     const bool pay = payloads != nullptr;
+    if (!options_ok(opt)) return fail(SM_ERR_ARG, "sm_options.reserved must be zero");
     Plan pl;
     int rc = make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
                        pick_tile(dtype, pay, opt), &pl);
@@ -299,7 +308,8 @@ int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t 
 
 size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,
                                             int has_payload, const sm_options* opt) {
-    if (!dtype_ok(dtype) || count < 0 || total < 0 || total > (1ll << 40)) return 0;
+    if (!dtype_ok(dtype) || !options_ok(opt) || count < 0 || total < 0 || total > (1ll << 40))
+        return 0;
     const bool pay = has_payload != 0;
     const int32_t tile = pick_tile(dtype, pay, opt);
     if (check_tile(dtype, pay, tile) != SM_OK) return 0;
@@ -316,6 +326,7 @@ int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64
         return fail(SM_ERR_ARG, "count and total must be >= 0 (count=%lld, total=%lld)",
                     (long long)count, (long long)total);
     if (count > (1ll << 31) - 2) return fail(SM_ERR_ARG, "too many pairs");
+    if (!options_ok(opt)) return fail(SM_ERR_ARG, "sm_options.reserved must be zero");
     const bool pay = payloads != nullptr;
     const int32_t tile = pick_tile(dtype, pay, opt);
     int rc = check_tile(dtype, pay, tile);
@@ -364,6 +375,7 @@ int sort_plan(int64_t N, int dtype, bool pay, const sm_options* opt, int* run, i
               sm::SortLayout* L, int64_t seg_count = 0, int64_t max_len = 0) {
     if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
     if (N < 0 || N >= (1ll << 31)) return fail(SM_ERR_ARG, "N must be in [0, 2^31)");
+    if (!options_ok(opt)) return fail(SM_ERR_ARG, "sm_options.reserved must be zero");
     *run = opt && opt->run != 0 ? opt->run : 512;
     if (!sm::sort_run_ok(*run, dtype))
         return fail(SM_ERR_ARG, "run must be 256, 512, 1024, 2048 or (32-bit keys) 4096");

@@ -196,3 +196,18 @@ def test_sort_learned_error_paths(sm):
     assert call(opts=sm._opts(descending=True)) == -1
     assert call(ws_bytes=8) == -4
     assert call(N=0) == 0
+
+
+def test_reserved_options_rejected(sm):
+    import torch
+    o = sm.Options()
+    o.reserved[2] = 1
+    assert call_merge(sm, opts=o) == -1
+    assert sm._lib.stable_merge_workspace_bytes(10, 10, 1, 0, ctypes.byref(o)) == 0
+    assert sm._lib.stable_merge_batched_workspace_bytes(2, 10, 1, 0, ctypes.byref(o)) == 0
+    assert sm._lib.stable_merge_sort_workspace_bytes(100, 1, 0, ctypes.byref(o)) == 0
+    assert sm._lib.stable_merge_segmented_sort_workspace_bytes(2, 100, 60, 1, 0,
+                                                                ctypes.byref(o)) == 0
+    assert sm._lib.stable_merge_sort(0x10000, None, 100, 0x20000, None, 1, 0x30000, 1 << 20,
+                                     ctypes.byref(o), None) == -1
+    assert sm.workspace_bytes(10, 10, torch.uint32) > 0
