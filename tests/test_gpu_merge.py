@@ -120,6 +120,20 @@ def test_forced_p(p):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_subproblem_sizes_across_kernels(dtype, with_pay):
+    """Forced block counts whose subproblems span every merge kernel: the
+    register-pipelined one, the nine-chunk one, the
+    one-workgroup-per-subproblem one and the second-level split."""
+    g = np.random.default_rng(44)
+    A, B = rand_sorted(g, 60_001, 500, dtype), rand_sorted(g, 59_999, 500, dtype)
+    for blk in (1000, 2600, 3000, 4100, 6000, 8200, 12_000, 30_000):
+        p = max(1, -(-len(A) // blk))
+        flush(f"subproblem sizes dtype={np.dtype(dtype).name} pay={with_pay} block={blk} p={p}")
+        check(A, B, with_pay, p_a=p, p_b=p)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_forced_few_blocks_large(dtype):
     """Few forced blocks over large arrays: subproblems far beyond one
     workgroup are split again by the method (two levels)."""
