@@ -115,8 +115,10 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
         wait_vm<0>();
         commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
         __syncthreads();
+        __builtin_amdgcn_s_setprio(2);   // memory phase first, as in merge_pipelined
         if (more) prefetch<K, PAY, L, R>(nxt, keys, (uint64_t)nkeys, pay, rk, rp);
         if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+        __builtin_amdgcn_s_setprio(0);
         if (cur.s > 0) merge_lanes<K, PAY, L>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
         prev = cur;
         cur = nxt;
@@ -176,8 +178,12 @@ __device__ __forceinline__ void merge_pipelined(
         wait_vm<PAY ? 2 * R : R>();
         commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
         __syncthreads();
+        // the memory phase runs at raised priority, so that the waves of a
+        // SIMD issue their stores and loads before the others' merges
+        __builtin_amdgcn_s_setprio(2);
         if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
         prefetch_whole<K, PAY, L, R>(nn, rkeys, rpay, rk, rp);
+        __builtin_amdgcn_s_setprio(0);
         if (cur.s > 0)
             merge_lanes<K, PAY, L, (!PAY || R <= 3)>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx,
                                                     sp.sXb, sp.sYb);
