@@ -112,10 +112,10 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
         // one wait for everything in flight (this piece's loads, and stores
         // issued a whole merge ago): afterwards no register has a load pending,
         // so the compiler adds no waits further down the iteration
+        __builtin_amdgcn_s_setprio(2);   // staging and memory first, as in merge_pipelined
         wait_vm<0>();
         commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
         __syncthreads();
-        __builtin_amdgcn_s_setprio(2);   // memory phase first, as in merge_pipelined
         if (more) prefetch<K, PAY, L, R>(nxt, keys, (uint64_t)nkeys, pay, rk, rp);
         if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
         __builtin_amdgcn_s_setprio(0);
@@ -175,12 +175,13 @@ __device__ __forceinline__ void merge_pipelined(
     prefetch_whole<K, PAY, L, R>(nxt, rkeys, rpay, rkB, rpB);
     auto step = [&](u32x4 (&rk)[R], u32x4 (&rp)[R], int64_t w) {
         const SegPlan nn = plan_of(w + 2 * G);
+        // the staging and memory phase runs at raised priority, so that the
+        // waves of a SIMD commit, pass the barrier and issue their stores
+        // and loads before the others' merges
+        __builtin_amdgcn_s_setprio(2);
         wait_vm<PAY ? 2 * R : R>();
         commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
         __syncthreads();
-        // the memory phase runs at raised priority, so that the waves of a
-        // SIMD issue their stores and loads before the others' merges
-        __builtin_amdgcn_s_setprio(2);
         if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
         prefetch_whole<K, PAY, L, R>(nn, rkeys, rpay, rk, rp);
         __builtin_amdgcn_s_setprio(0);
