@@ -740,6 +740,9 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int dPay = DIRECT ? (int)(sPay - reinterpret_cast<const uint32_t*>(sKey)) : 0;
 
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
+    // (the searches are short chains of LDS reads that end at a barrier:
+    // they run above the merges of other workgroups)
+    __builtin_amdgcn_s_setprio(1);
     const LaneBlocks<L, LEAN> LA(a), LB(b);
     {
         const int xt = LA.start(t), yt = LB.start(t);
@@ -756,6 +759,7 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
         }
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
 
     // the sentinel loop is exact unless the A successor is the type maximum
     // and the B part holds that maximum too
