@@ -591,7 +591,8 @@ __device__ __forceinline__ void stage_direct(const SegPlan& p, const K* keys, ui
 // segment.
 template <typename K, bool PAY, bool DIRECT>
 __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint32_t* sIdx,
-                                                    int dPay, int ia1, int ib1, int len1, int co1,
+                                                    int dPay, const uint32_t* sPay, int dA, int dB,
+                                                    int ia1, int ib1, int len1, int co1,
                                                     int cp1, int ia2, int ib2, int len2, int co2,
                                                     int cp2) {
     const int len = len1 > len2 ? len1 : len2;
@@ -642,8 +643,11 @@ __device__ __forceinline__ void lane_merge_uniform2(const K* sKey, K* sOut, uint
         sOut[co1 + k] = t1 ? kb1 : ka1;
         sOut[co2 + k] = t2 ? kb2 : ka2;
         if (PAY) {
-            sIdx[cp1 + k] = (uint32_t)s1;
-            sIdx[cp2 + k] = (uint32_t)s2;
+            // the payload of key slot s sits at payload slot s + dA (A) or
+            // s + dB (B); past the end of a lane's range the value read is
+            // never written back
+            sIdx[cp1 + k] = sPay[s1 + (t1 ? dB : dA)];
+            sIdx[cp2 + k] = sPay[s2 + (t2 ? dB : dA)];
         }
         const int n1 = s1 + 1, n2 = s2 + 1;
         const K kn1 = sKey[n1];
@@ -701,6 +705,7 @@ struct OddEvenMerge {
 // Bounds-checked form: each lane stops after its own la + lb outputs.
 template <typename K, bool PAY, bool DIRECT>
 __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint32_t* sIdx, int dPay,
+                                                   const uint32_t* sPay, int dA, int dB,
                                                    int ia, int la, int ib, int lb, int co, int cp) {
     const int len = la + lb;
     const int ea = ia + la, eb = ib + lb;
@@ -711,7 +716,7 @@ __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint3
         const int src = takeB ? ib : ia;
         sOut[co + k] = takeB ? kb : ka;
         if constexpr (DIRECT) sIdx[cp + k] = reinterpret_cast<const uint32_t*>(sKey)[src + dPay];
-        else if (PAY) sIdx[cp + k] = (uint32_t)src;
+        else if (PAY) sIdx[cp + k] = sPay[src + (takeB ? dB : dA)];
         const int nxt = src + 1;
         const K kn = sKey[nxt];
         if (takeB) { ib = nxt; kb = kn; }
@@ -734,10 +739,14 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int a = p.a, b = p.b, s = p.s;
     const int baseA = p.offA, baseB = p.wa + p.offB;
     // 32-bit keys: payload slot = key slot + dPay (the payload windows share
-    // the key windows' geometry), so the merges write payloads themselves;
-    // otherwise they write key slots and a gather pass follows
+    // the key windows' geometry, and dPay is the distance between the two
+    // arrays in LDS); 64-bit keys: payload slot = key slot + dA in A's window
+    // and + dB in B's (payload chunks hold twice as many elements as key
+    // chunks).  Either way the merges write the payloads themselves.
     constexpr bool DIRECT = PAY && sizeof(K) == 4;
     const int dPay = DIRECT ? (int)(sPay - reinterpret_cast<const uint32_t*>(sKey)) : 0;
+    const int dA = p.offPA - p.offA;
+    const int dB = (p.waP + p.offPB) - (p.wa + p.offB);
 
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
     // (the searches are short chains of LDS reads that end at a barrier:
@@ -781,30 +790,20 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int la3 = ok3 ? p3.a_hi - p3.a_lo : 0, lb3 = ok3 ? p3.b_hi - p3.b_lo : 0;
     const int la4 = ok4 ? p4.a_hi - p4.a_lo : 0, lb4 = ok4 ? p4.b_hi - p4.b_lo : 0;
     if (fast) {
-        lane_merge_uniform2<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, baseA + p3.a_lo,
+        lane_merge_uniform2<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, sPay, dA, dB, baseA + p3.a_lo,
                                             baseB + p3.b_lo, la3 + lb3, p.offC + p3.c_off,
                                             p.offCP + p3.c_off, baseA + p4.a_lo, baseB + p4.b_lo,
                                             la4 + lb4, p.offC + p4.c_off, p.offCP + p4.c_off);
     } else {
-        lane_merge_checked<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, baseA + p3.a_lo, la3,
+        lane_merge_checked<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, sPay, dA, dB, baseA + p3.a_lo, la3,
                                            baseB + p3.b_lo, lb3, p.offC + p3.c_off,
                                            p.offCP + p3.c_off);
-        lane_merge_checked<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, baseA + p4.a_lo, la4,
+        lane_merge_checked<K, PAY, DIRECT>(sKey, sOut, sIdx, dPay, sPay, dA, dB, baseA + p4.a_lo, la4,
                                            baseB + p4.b_lo, lb4, p.offC + p4.c_off,
                                            p.offCP + p4.c_off);
     }
     __syncthreads();
 
-    if (PAY && !DIRECT) {
-        // gather: key slot of each output -> its payload (same element in the
-        // payload window geometry), in place
-        for (int k = t; k < s; k += L) {
-            const int si = (int)sIdx[p.offCP + k];
-            const int ps = si < p.wa ? si - p.offA + p.offPA : si - p.wa - p.offB + p.waP + p.offPB;
-            sIdx[p.offCP + k] = sPay[ps];
-        }
-        __syncthreads();
-    }
 }
 
 // One output array of a subproblem, LDS -> HBM: aligned 16-byte stores for
