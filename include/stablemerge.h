@@ -394,6 +394,73 @@ SM_API int stable_merge_sort_learned(const void *keys, const uint32_t *payloads,
                                      void *ws, size_t ws_bytes, const sm_options *opt,
                                      void *stream);
 
+/* ------------------------------------------------------------------------
+ * Rank-model handles (an addition to the paper, beside the plain 97-float
+ * arrays above).  A handle keeps a network together with what it models:
+ * the key type, which rank it predicts (rank_low, as for A's block starts
+ * searched in B, or rank_high, as for B's block starts searched in A), its
+ * feature kind and the length of the array it was trained on, so that a
+ * trained model can be saved, loaded and reused as one unit.  The library owns a handle and its 98 device floats (the 97
+ * parameters, then the last training loss); everything else stays the
+ * caller's.  Handles are not thread-safe: one thread at a time per handle.
+ * ------------------------------------------------------------------------ */
+typedef struct sm_predictor sm_predictor;
+
+/* Size of a saved model: a 40-byte header (magic "SMRM", format version 1,
+ * key type, is_high, feature kind 1 = log2(u + 1) / bits, hidden width 32,
+ * parameter count 97, the last loss as float, the trained array length as
+ * int64), the 97 parameters as little-endian floats, and an FNV-1a checksum
+ * of everything before it. */
+#define SM_PREDICTOR_BLOB_BYTES 432
+
+/*
+ * Allocates a handle for keys of `dtype` that predicts rank_high (is_high
+ * != 0) or rank_low positions; its parameters start at zero (a constant
+ * prediction of rank 0) and its loss at 1.  Allocates device memory on the
+ * current device (synchronous).  *out is NULL on failure.
+ */
+SM_API int sm_predictor_create(sm_predictor **out, int dtype, int is_high);
+
+/* Frees a handle and its device memory; NULL is a no-op. */
+SM_API int sm_predictor_destroy(sm_predictor *p);
+
+/*
+ * sm_rank_model_train into the handle: trains a model of the sorted
+ * X[0, len) for queries from Q[0, q_len) with the handle's key type and
+ * rank kind; the loss is kept in the handle.  Asynchronous on `stream`;
+ * workspace as sm_rank_model_train (sm_rank_model_workspace_bytes).
+ */
+SM_API int sm_predictor_train(sm_predictor *p, const void *X, int64_t len, const void *Q,
+                              int64_t q_len, int64_t samples, int64_t steps, float lr,
+                              uint64_t seed, void *ws, size_t ws_bytes, void *stream);
+
+/* The handle's 97 device parameters, for the calls that take a model
+ * (stable_merge_learned, stable_merge_partition_learned, ...); NULL for an
+ * invalid handle.  Valid until sm_predictor_destroy. */
+SM_API const float *sm_predictor_params(const sm_predictor *p);
+
+/* Key type, rank kind, trained array length and last loss of a handle (any
+ * output pointer may be NULL).  Reading the loss waits for the handle's
+ * last training run. */
+SM_API int sm_predictor_info(const sm_predictor *p, int *dtype, int *is_high,
+                             int64_t *trained_len, float *loss);
+
+/*
+ * Writes the SM_PREDICTOR_BLOB_BYTES-byte saved form of a handle into the
+ * host buffer host_buf (bytes >= SM_PREDICTOR_BLOB_BYTES, else SM_ERR_ARG).
+ * Waits for the handle's last training run (synchronous).
+ */
+SM_API int sm_predictor_save(const sm_predictor *p, void *host_buf, size_t bytes);
+
+/*
+ * Creates a handle from a saved form: checks the magic, the version, the
+ * checksum and that the network shape and feature kind are the ones this
+ * library evaluates (SM_ERR_ARG otherwise, SM_ERR_DTYPE for an unknown key
+ * type), then uploads the parameters to the current device (synchronous).
+ * A loaded handle predicts exactly what the saved one did.
+ */
+SM_API int sm_predictor_load(sm_predictor **out, const void *host_buf, size_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

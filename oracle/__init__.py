@@ -10,7 +10,11 @@ The arithmetic lives in ``oracle.c`` (plain C, built by ``build_oracle``) and,
 for the learned cross-rank predictor, in ``oracle/mlp.py`` (numpy, FP64).
 This module only marshals numpy arrays into those C routines.
 
-Key types: ``0`` = int32 (signed order), ``1`` = uint32, ``2`` = uint64.
+Key types: ``0`` = int32 (signed order), ``1`` = uint32, ``2`` = uint64,
+``3`` = int64, ``4`` = float32, ``5`` = float64 (IEEE 754 totalOrder).  The
+routines that order keys take ``descending=True`` for non-increasing order
+(``DESCENDING`` added to the key type code): ties still keep A before B and
+each source's own order.
 """
 from __future__ import annotations
 
@@ -25,6 +29,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 INT32, UINT32, UINT64, INT64, FLOAT32, FLOAT64 = 0, 1, 2, 3, 4, 5
+DESCENDING = 8
 NP_DTYPE = {INT32: np.int32, UINT32: np.uint32, UINT64: np.uint64, INT64: np.int64,
             FLOAT32: np.float32, FLOAT64: np.float64}
 
@@ -94,6 +99,10 @@ def dtype_code(arr: np.ndarray) -> int:
     raise TypeError(f"unsupported key dtype {arr.dtype}")
 
 
+def _code(arr: np.ndarray, descending: bool = False) -> int:
+    return dtype_code(arr) | (DESCENDING if descending else 0)
+
+
 def _ptr(a):
     return None if a is None else a.ctypes.data
 
@@ -104,21 +113,21 @@ def _c(a, dtype=None):
     return np.ascontiguousarray(a if dtype is None else a.astype(dtype, copy=False))
 
 
-def rank_low(x, X: np.ndarray) -> int:
-    """rank_low(x, X): number of elements of X strictly smaller than x."""
+def rank_low(x, X: np.ndarray, descending: bool = False) -> int:
+    """rank_low(x, X): number of elements of X strictly before x in the order."""
     X = _c(X)
     xa = np.array([x], dtype=X.dtype)
-    return int(_load().orc_rank_low(_ptr(xa), 0, _ptr(X), len(X), dtype_code(X)))
+    return int(_load().orc_rank_low(_ptr(xa), 0, _ptr(X), len(X), _code(X, descending)))
 
 
-def rank_high(x, X: np.ndarray) -> int:
-    """rank_high(x, X): number of elements of X smaller than or equal to x."""
+def rank_high(x, X: np.ndarray, descending: bool = False) -> int:
+    """rank_high(x, X): number of elements of X before or equal to x in the order."""
     X = _c(X)
     xa = np.array([x], dtype=X.dtype)
-    return int(_load().orc_rank_high(_ptr(xa), 0, _ptr(X), len(X), dtype_code(X)))
+    return int(_load().orc_rank_high(_ptr(xa), 0, _ptr(X), len(X), _code(X, descending)))
 
 
-def merge(A, B, pa=None, pb=None):
+def merge(A, B, pa=None, pb=None, descending: bool = False):
     """O1: stable two-pointer merge.  Returns (C, pc) (pc is None without payloads)."""
     A, B = _c(A), _c(B)
     assert A.dtype == B.dtype
@@ -127,7 +136,7 @@ def merge(A, B, pa=None, pb=None):
     C = np.empty(len(A) + len(B), dtype=A.dtype)
     pc = np.empty(len(C), dtype=np.uint32) if has_p else None
     _load().orc_merge(_ptr(A), _ptr(pa), len(A), _ptr(B), _ptr(pb), len(B),
-                      _ptr(C), _ptr(pc), dtype_code(A))
+                      _ptr(C), _ptr(pc), _code(A, descending))
     return C, pc
 
 
@@ -152,13 +161,13 @@ def block_of(length: int, p: int, k: int) -> int:
     return int(_load().orc_block_of(length, p, k))
 
 
-def cross_ranks(A, B, p_a: int, p_b: int | None = None):
+def cross_ranks(A, B, p_a: int, p_b: int | None = None, descending: bool = False):
     """Steps 1-2: (xbar[p_a+1], ybar[p_b+1]) as int64 arrays."""
     p_b = p_a if p_b is None else p_b
     A, B = _c(A), _c(B)
     xbar = np.empty(p_a + 1, dtype=np.int64)
     ybar = np.empty(p_b + 1, dtype=np.int64)
-    _load().orc_cross_ranks(_ptr(A), len(A), _ptr(B), len(B), p_a, p_b, dtype_code(A),
+    _load().orc_cross_ranks(_ptr(A), len(A), _ptr(B), len(B), p_a, p_b, _code(A, descending),
                             _ptr(xbar), _ptr(ybar))
     return xbar, ybar
 
@@ -178,7 +187,8 @@ def pieces(n: int, m: int, p_a: int, p_b: int, xbar, ybar, two_select: bool = Fa
     return out
 
 
-def merge_by_pieces(A, B, p_a: int, p_b: int | None = None, pa=None, pb=None):
+def merge_by_pieces(A, B, p_a: int, p_b: int | None = None, pa=None, pb=None,
+                    descending: bool = False):
     """The method run sequentially: Steps 1-4, each subproblem merged with O1."""
     p_b = p_a if p_b is None else p_b
     A, B = _c(A), _c(B)
@@ -187,20 +197,20 @@ def merge_by_pieces(A, B, p_a: int, p_b: int | None = None, pa=None, pb=None):
     C = np.zeros(len(A) + len(B), dtype=A.dtype)
     pc = np.zeros(len(C), dtype=np.uint32) if has_p else None
     rc = _load().orc_merge_by_pieces(_ptr(A), _ptr(pa), len(A), _ptr(B), _ptr(pb), len(B),
-                                     p_a, p_b, _ptr(C), _ptr(pc), dtype_code(A))
+                                     p_a, p_b, _ptr(C), _ptr(pc), _code(A, descending))
     if rc != 0:
         raise AssertionError("a subproblem fell outside C")
     return C, pc
 
 
-def sort(keys, pay=None, run_len: int = 512):
+def sort(keys, pay=None, run_len: int = 512, descending: bool = False):
     """O4, method mirror: sort runs of run_len, then pairwise merge rounds."""
     keys = np.array(keys, copy=True)
     pay = None if pay is None else np.array(pay, dtype=np.uint32, copy=True)
     tk = np.empty_like(keys)
     tp = None if pay is None else np.empty_like(pay)
     _load().orc_sort(_ptr(keys), _ptr(pay), len(keys), run_len, _ptr(tk), _ptr(tp),
-                     dtype_code(keys))
+                     _code(keys, descending))
     return keys, pay
 
 

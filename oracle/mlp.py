@@ -129,6 +129,11 @@ def init_params(sample_phi_sorted: np.ndarray, sample_target: np.ndarray) -> np.
 
 
 def predict_rank(params, keys: np.ndarray, length: int) -> np.ndarray:
-    """Predicted rank clamp(round(y * length), 0, length)."""
+    """Predicted rank: y * length rounded to the nearest integer (halves to
+    even), clamped to [0, length]; 0 where y * length is not a number.  The
+    prediction only chooses where the corrective search starts, so any value
+    in [0, length] is a valid start."""
     y, _, _ = forward(params, features(keys))
-    return np.clip(np.rint(y * length), 0, length).astype(np.int64)
+    r = np.rint(np.asarray(y, dtype=np.float64) * float(length))
+    r = np.where(np.isnan(r), 0.0, r)
+    return np.clip(r, 0.0, float(length)).astype(np.int64)

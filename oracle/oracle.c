@@ -11,7 +11,12 @@
  * comparison function per key type, no blocking and no fusion.
  *
  * Key types (the order relation of Section 2, problem statement):
- *   0 = int32  (signed compare), 1 = uint32, 2 = uint64 (unsigned compare).
+ *   0 = int32  (signed compare), 1 = uint32, 2 = uint64 (unsigned compare),
+ *   3 = int64, 4 = float32, 5 = float64 (IEEE 754 totalOrder).
+ * Adding ORC_DESCENDING (8) to a key type reverses its order: "smaller" then
+ * means "later in non-increasing order", and every routine below (ranks,
+ * merges, sort) runs unchanged on that reversed relation.  Ties still keep
+ * A before B and each source's own order.
  * Payloads are uint32 values that travel with their key; NULL means none.
  *
  * Pinned by tests/test_oracle_*.py against: the Figure 1 worked example,
@@ -24,7 +29,7 @@
 #include <string.h>
 
 enum { ORC_INT32 = 0, ORC_UINT32 = 1, ORC_UINT64 = 2, ORC_INT64 = 3, ORC_FLOAT32 = 4,
-       ORC_FLOAT64 = 5 };
+       ORC_FLOAT64 = 5, ORC_DESCENDING = 8 };
 
 /* ------------------------------------------------------------------ */
 /* Element access                                                      */
@@ -32,6 +37,7 @@ enum { ORC_INT32 = 0, ORC_UINT32 = 1, ORC_UINT64 = 2, ORC_INT64 = 3, ORC_FLOAT32
 
 static size_t key_size(int dtype)
 {
+    dtype &= 7;
     return dtype == ORC_UINT64 || dtype == ORC_INT64 || dtype == ORC_FLOAT64 ? 8 : 4;
 }
 
@@ -52,8 +58,8 @@ static int total_order_lt(uint64_t a, uint64_t b, int bits)
     return na ? (a & mag) > (b & mag) : (a & mag) < (b & mag);
 }
 
-/* X[i] < Y[j] under the order of the key type. */
-static int key_lt(const void *X, int64_t i, const void *Y, int64_t j, int dtype)
+/* X[i] < Y[j] under the ascending order of the key type. */
+static int key_lt_asc(const void *X, int64_t i, const void *Y, int64_t j, int dtype)
 {
     switch (dtype) {
     case ORC_INT32:  return ((const int32_t *)X)[i]  < ((const int32_t *)Y)[j];
@@ -65,6 +71,14 @@ static int key_lt(const void *X, int64_t i, const void *Y, int64_t j, int dtype)
         return total_order_lt(((const uint64_t *)X)[i], ((const uint64_t *)Y)[j], 64);
     default:         return ((const uint64_t *)X)[i] < ((const uint64_t *)Y)[j];
     }
+}
+
+/* X[i] < Y[j] under the requested order: with ORC_DESCENDING, X[i] comes
+ * before Y[j] exactly when Y[j] < X[i] ascending. */
+static int key_lt(const void *X, int64_t i, const void *Y, int64_t j, int dtype)
+{
+    if (dtype & ORC_DESCENDING) return key_lt_asc(Y, j, X, i, dtype & 7);
+    return key_lt_asc(X, i, Y, j, dtype);
 }
 
 static void key_copy(void *dst, int64_t di, const void *src, int64_t si, int dtype)

@@ -1,6 +1,8 @@
 """Builds libstablemerge.so in-tree with hipcc for gfx950.
 
-Every HIP source under csrc/ is compiled in one hipcc invocation into a
+Every HIP source under csrc/ is compiled to an object of its own (in
+parallel; each source holds its kernels and their launchers, so no
+relocatable device code is needed), then the objects are linked into a
 shared library next to this file.  Packed FP32 instructions are disabled
 (``-packed-fp32-ops``) for all device code.
 """
@@ -21,16 +23,20 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def hipcc_command(out: str):
-    return (["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-             "-Wall", "-Wno-unused-function", "-fvisibility=hidden",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-I", os.path.join(ROOT, "include"), "-o", out] + sources())
+COMPILE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
+                 "-Wno-unused-function", "-fvisibility=hidden",
+                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build_library(verbose: bool = False) -> str:
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = hipcc_command(tmp)
+def compile_command(src: str, obj: str):
+    return ["hipcc"] + COMPILE_FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+
+
+def link_command(objs, out: str):
+    return ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out] + list(objs)
+
+
+def _run(cmd, verbose: bool, what: str):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -38,9 +44,25 @@ def build_library(verbose: bool = False) -> str:
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         sys.stderr.write(err + "\n")
-        raise RuntimeError("hipcc failed to build libstablemerge.so")
+        raise RuntimeError(f"hipcc failed: {what}")
     if err.strip() and verbose:
         sys.stderr.write(err + "\n")
+
+
+def build_library(verbose: bool = False, jobs: int = 0) -> str:
+    import concurrent.futures
+    import tempfile
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 1)))
+    with tempfile.TemporaryDirectory(prefix="sm_build_") as td:
+        objs = [os.path.join(td, os.path.basename(s) + ".o") for s in srcs]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            futs = [ex.submit(_run, compile_command(s, o), verbose, os.path.basename(s))
+                    for s, o in zip(srcs, objs)]
+            for f in futs:
+                f.result()
+        tmp = LIB + f".tmp{os.getpid()}"
+        _run(link_command(objs, tmp), verbose, "link")
     os.replace(tmp, LIB)
     return LIB
 

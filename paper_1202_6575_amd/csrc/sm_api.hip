@@ -14,6 +14,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <new>
+
 #include "stablemerge.h"
 #include "sm_batch.h"
 #include "sm_device.h"
@@ -175,6 +177,22 @@ int check_ws(const void* ws, size_t ws_bytes, size_t need) {
     return SM_OK;
 }
 
+// The workspace holds cross ranks and descriptors that the kernels write
+// while reading the inputs and writing the outputs: it must not share a byte
+// with any of the caller's arrays.
+int check_ws_alias(const void* ws, size_t need, const void* keys, const uint32_t* payloads,
+                   int64_t total, const void* out_keys, const uint32_t* out_payloads, int dtype,
+                   const void* extra0 = nullptr, size_t extra0_bytes = 0,
+                   const void* extra1 = nullptr, size_t extra1_bytes = 0) {
+    const size_t kb = (size_t)total * key_bytes(dtype), pb = (size_t)total * 4;
+    if (overlap(ws, need, keys, kb) || overlap(ws, need, out_keys, kb) ||
+        overlap(ws, need, payloads, payloads ? pb : 0) ||
+        overlap(ws, need, out_payloads, out_payloads ? pb : 0) ||
+        overlap(ws, need, extra0, extra0_bytes) || overlap(ws, need, extra1, extra1_bytes))
+        return fail(SM_ERR_ALIAS, "workspace overlaps an input or output array");
+    return SM_OK;
+}
+
 // Steps 3-4 and the merges, once Steps 1-2 have written xbar / ybar.
 // `tail` is the workspace from the descriptors on; dtype is a kernel code.
 int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t* payloads,
@@ -261,6 +279,10 @@ int stable_merge_pieces(const void* keys, const uint32_t* payloads, int64_t n, i
     if (rc != SM_OK) return rc;
     rc = check_ws(ws, ws_bytes, pl.ws_bytes - pl.off_desc);
     if (rc != SM_OK) return rc;
+    rc = check_ws_alias(ws, pl.ws_bytes - pl.off_desc, keys, payloads, n + m, out_keys,
+                        out_payloads, dtype, xbar, (size_t)(p_a + 1) * 8, ybar,
+                        (size_t)(p_b + 1) * 8);
+    if (rc != SM_OK) return rc;
     return cases_and_merge(pl, dtype, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
                            static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
@@ -279,6 +301,8 @@ int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t 
     rc = check_buffers(keys, payloads, total, out_keys, out_payloads, dtype);
     if (rc != SM_OK) return rc;
     rc = check_ws(ws, ws_bytes, pl.ws_bytes);
+    if (rc != SM_OK) return rc;
+    rc = check_ws_alias(ws, pl.ws_bytes, keys, payloads, total, out_keys, out_payloads, dtype);
     if (rc != SM_OK) return rc;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -340,6 +364,9 @@ int stable_merge_batched(const void* keys, const uint32_t* payloads, const int64
         return fail(SM_ERR_ARG, "too many subproblems for one launch; use a larger tile");
     const size_t off_eng = align256((size_t)count * sm::kPieceDescBytes);
     rc = check_ws(ws, ws_bytes, off_eng + L.bytes);
+    if (rc != SM_OK) return rc;
+    rc = check_ws_alias(ws, off_eng + L.bytes, keys, payloads, total, out_keys, out_payloads,
+                        dtype, offsets, (size_t)(count + 1) * 8, n_a, (size_t)count * 8);
     if (rc != SM_OK) return rc;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -663,6 +690,8 @@ int stable_merge_learned(const void* keys, const uint32_t* payloads, int64_t n, 
     if (need == 0) return fail(SM_ERR_ARG, "sizes not supported");
     rc = check_ws(ws, ws_bytes, need);
     if (rc != SM_OK) return rc;
+    rc = check_ws_alias(ws, need, keys, payloads, n + m, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
     const int64_t p_a = n > 0 ? (n + block - 1) / block : 1;
     const int64_t p_b = m > 0 ? (m + block - 1) / block : 1;
     int64_t* xbar = static_cast<int64_t*>(ws);
@@ -673,6 +702,192 @@ int stable_merge_learned(const void* keys, const uint32_t* payloads, int64_t n, 
     if (rc != SM_OK) return rc;
     return stable_merge_pieces(keys, payloads, n, m, p_a, p_b, xbar, ybar, out_keys, out_payloads,
                                dtype, static_cast<char*>(ws) + off, ws_bytes - off, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Rank-model handles: a trained network together with what it was trained
+// for (key type, which rank, feature kind), so that it can be kept, saved
+// and loaded as a unit.  The parameters live in 98 device floats owned by
+// the handle: the 97 parameters, then the last training loss.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct sm_predictor {
+    uint32_t magic;
+    int dtype;
+    int is_high;
+    int device;
+    int64_t trained_len;
+    float* dev;            // 97 parameters, then the loss
+    hipStream_t stream;    // stream of the last training run
+};
+
+namespace {
+
+constexpr uint32_t kPredMagic = 0x4D524D53u;   // "SMRM" read little-endian
+constexpr uint32_t kBlobVersion = 1;
+constexpr int32_t kFeatureLog2 = 1;            // phi = log2(u + 1) / bits
+constexpr size_t kBlobParamsOff = 40;
+constexpr size_t kBlobChecksumOff = kBlobParamsOff + 4 * SM_MLP_PARAMS;
+static_assert(kBlobChecksumOff + 4 == SM_PREDICTOR_BLOB_BYTES, "blob layout");
+
+uint32_t fnv1a(const unsigned char* b, size_t n) {
+    uint32_t h = 2166136261u;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 16777619u;
+    }
+    return h;
+}
+
+template <typename T>
+void put(unsigned char* b, size_t off, T v) { memcpy(b + off, &v, sizeof v); }
+template <typename T>
+T get(const unsigned char* b, size_t off) {
+    T v;
+    memcpy(&v, b + off, sizeof v);
+    return v;
+}
+
+bool pred_ok(const sm_predictor* p) { return p && p->magic == kPredMagic && p->dev; }
+
+int pred_new(sm_predictor** out, int dtype, int is_high, int64_t trained_len,
+             const float* host_vals) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    float* d = nullptr;
+    e = hipMalloc(&d, (SM_MLP_PARAMS + 1) * sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "predictor allocation");
+    e = hipMemcpy(d, host_vals, (SM_MLP_PARAMS + 1) * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "predictor upload");
+    }
+    sm_predictor* p = new (std::nothrow) sm_predictor;
+    if (!p) {
+        (void)hipFree(d);
+        return fail(SM_ERR_ARG, "out of host memory");
+    }
+    p->magic = kPredMagic;
+    p->dtype = dtype;
+    p->is_high = is_high;
+    p->device = dev;
+    p->trained_len = trained_len;
+    p->dev = d;
+    p->stream = nullptr;
+    *out = p;
+    return SM_OK;
+}
+
+// Wait for the last training run, then copy the parameters and the loss.
+int pred_download(const sm_predictor* p, float* host_vals) {
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(host_vals, p->dev, (SM_MLP_PARAMS + 1) * sizeof(float),
+                      hipMemcpyDeviceToHost);
+    return e == hipSuccess ? SM_OK : hip_fail(e, "predictor download");
+}
+
+}  // namespace
+
+extern "C" {
+
+int sm_predictor_create(sm_predictor** out, int dtype, int is_high) {
+    if (!out) return fail(SM_ERR_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    float zeros[SM_MLP_PARAMS + 1] = {};
+    zeros[SM_MLP_PARAMS] = 1.0f;   // an untrained model: loss 1 (error of the whole array)
+    return pred_new(out, dtype, is_high != 0, 0, zeros);
+}
+
+int sm_predictor_destroy(sm_predictor* p) {
+    if (!p) return SM_OK;
+    if (p->magic != kPredMagic) return fail(SM_ERR_ARG, "not a predictor handle");
+    p->magic = 0;
+    const hipError_t e = hipFree(p->dev);
+    delete p;
+    return e == hipSuccess ? SM_OK : hip_fail(e, "predictor free");
+}
+
+int sm_predictor_train(sm_predictor* p, const void* X, int64_t len, const void* Q, int64_t q_len,
+                       int64_t samples, int64_t steps, float lr, uint64_t seed, void* ws,
+                       size_t ws_bytes, void* stream) {
+    if (!pred_ok(p)) return fail(SM_ERR_ARG, "not a predictor handle");
+    const int rc = sm_rank_model_train(X, len, Q, q_len, p->dtype, p->is_high, samples, steps, lr,
+                                       seed, p->dev, p->dev + SM_MLP_PARAMS, ws, ws_bytes, stream);
+    if (rc != SM_OK) return rc;
+    p->trained_len = len;
+    p->stream = static_cast<hipStream_t>(stream);
+    return SM_OK;
+}
+
+const float* sm_predictor_params(const sm_predictor* p) { return pred_ok(p) ? p->dev : nullptr; }
+
+int sm_predictor_info(const sm_predictor* p, int* dtype, int* is_high, int64_t* trained_len,
+                      float* loss) {
+    if (!pred_ok(p)) return fail(SM_ERR_ARG, "not a predictor handle");
+    if (dtype) *dtype = p->dtype;
+    if (is_high) *is_high = p->is_high;
+    if (trained_len) *trained_len = p->trained_len;
+    if (loss) {
+        float v[SM_MLP_PARAMS + 1];
+        const int rc = pred_download(p, v);
+        if (rc != SM_OK) return rc;
+        *loss = v[SM_MLP_PARAMS];
+    }
+    return SM_OK;
+}
+
+int sm_predictor_save(const sm_predictor* p, void* host_buf, size_t bytes) {
+    if (!pred_ok(p)) return fail(SM_ERR_ARG, "not a predictor handle");
+    if (!host_buf || bytes < SM_PREDICTOR_BLOB_BYTES)
+        return fail(SM_ERR_ARG, "the buffer must hold SM_PREDICTOR_BLOB_BYTES (%d) bytes",
+                    SM_PREDICTOR_BLOB_BYTES);
+    float v[SM_MLP_PARAMS + 1];
+    const int rc = pred_download(p, v);
+    if (rc != SM_OK) return rc;
+    unsigned char b[SM_PREDICTOR_BLOB_BYTES] = {};
+    put<uint32_t>(b, 0, kPredMagic);
+    put<uint32_t>(b, 4, kBlobVersion);
+    put<int32_t>(b, 8, p->dtype);
+    put<int32_t>(b, 12, p->is_high);
+    put<int32_t>(b, 16, kFeatureLog2);
+    put<int32_t>(b, 20, SM_MLP_HIDDEN);
+    put<int32_t>(b, 24, SM_MLP_PARAMS);
+    put<float>(b, 28, v[SM_MLP_PARAMS]);
+    put<int64_t>(b, 32, p->trained_len);
+    memcpy(b + kBlobParamsOff, v, 4 * SM_MLP_PARAMS);
+    put<uint32_t>(b, kBlobChecksumOff, fnv1a(b, kBlobChecksumOff));
+    memcpy(host_buf, b, SM_PREDICTOR_BLOB_BYTES);
+    return SM_OK;
+}
+
+int sm_predictor_load(sm_predictor** out, const void* host_buf, size_t bytes) {
+    if (!out) return fail(SM_ERR_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!host_buf || bytes < SM_PREDICTOR_BLOB_BYTES)
+        return fail(SM_ERR_ARG, "a predictor blob has SM_PREDICTOR_BLOB_BYTES (%d) bytes",
+                    SM_PREDICTOR_BLOB_BYTES);
+    const unsigned char* b = static_cast<const unsigned char*>(host_buf);
+    if (get<uint32_t>(b, 0) != kPredMagic) return fail(SM_ERR_ARG, "not a predictor blob");
+    if (get<uint32_t>(b, 4) != kBlobVersion)
+        return fail(SM_ERR_ARG, "predictor blob version %u is not supported",
+                    get<uint32_t>(b, 4));
+    if (get<uint32_t>(b, kBlobChecksumOff) != fnv1a(b, kBlobChecksumOff))
+        return fail(SM_ERR_ARG, "predictor blob checksum mismatch");
+    const int dtype = get<int32_t>(b, 8), is_high = get<int32_t>(b, 12);
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "predictor blob names dtype %d", dtype);
+    if ((is_high != 0 && is_high != 1) || get<int32_t>(b, 16) != kFeatureLog2 ||
+        get<int32_t>(b, 20) != SM_MLP_HIDDEN || get<int32_t>(b, 24) != SM_MLP_PARAMS)
+        return fail(SM_ERR_ARG, "predictor blob describes a different network");
+    const int64_t len = get<int64_t>(b, 32);
+    if (len < 0) return fail(SM_ERR_ARG, "predictor blob has a negative array length");
+    float v[SM_MLP_PARAMS + 1];
+    memcpy(v, b + kBlobParamsOff, 4 * SM_MLP_PARAMS);
+    v[SM_MLP_PARAMS] = get<float>(b, 28);
+    return pred_new(out, dtype, is_high, len, v);
 }
 
 }  // extern "C"

@@ -52,11 +52,38 @@ _lib.stable_merge_learned.argtypes = [_vp, _vp, _i64, _i64, _vp, _vp, _i32, _vp,
                                       _i64, _i64, _vp, _vp, _vp, _sz, _vp]
 _lib.stable_merge_learned_workspace_bytes.restype = _sz
 _lib.stable_merge_learned_workspace_bytes.argtypes = [_i64, _i64, _i64, _i32, _i32]
+_pp = ctypes.POINTER(ctypes.c_void_p)
+_lib.sm_predictor_create.restype = _i32
+_lib.sm_predictor_create.argtypes = [_pp, _i32, _i32]
+_lib.sm_predictor_destroy.restype = _i32
+_lib.sm_predictor_destroy.argtypes = [_vp]
+_lib.sm_predictor_train.restype = _i32
+_lib.sm_predictor_train.argtypes = [_vp, _vp, _i64, _vp, _i64, _i64, _i64, _f32, _u64, _vp, _sz,
+                                    _vp]
+_lib.sm_predictor_params.restype = _vp
+_lib.sm_predictor_params.argtypes = [_vp]
+_lib.sm_predictor_info.restype = _i32
+_lib.sm_predictor_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                   ctypes.POINTER(_i64), ctypes.POINTER(_f32)]
+_lib.sm_predictor_save.restype = _i32
+_lib.sm_predictor_save.argtypes = [_vp, _vp, _sz]
+_lib.sm_predictor_load.restype = _i32
+_lib.sm_predictor_load.argtypes = [_pp, _vp, _sz]
+BLOB_BYTES = 432
 
 
 def _f32_params(p):
     if p.dtype != torch.float32 or p.numel() != NPARAM or not p.is_cuda or not p.is_contiguous():
         raise SMError(-1, "params must be a contiguous device float32 tensor of 97 entries")
+
+
+def _model_ptr(model):
+    """Device address of a model: a Predictor handle or a tensor of 97
+    device floats."""
+    if isinstance(model, Predictor):
+        return model.ptr()
+    _f32_params(model)
+    return _ptr(model)
 
 
 def mlp_grad(params, keys, target, *, stream=None):
@@ -143,8 +170,7 @@ def partition_learned(keys, n, m, p_a, p_b, model_b, model_a, step0_a=1, step0_b
     """Steps 1-2 from learned starting points.  Returns (xbar, ybar, hist,
     counters) with counters = [searches, fallbacks, probes]; hist and
     counters are accumulated into when given."""
-    _f32_params(model_b)
-    _f32_params(model_a)
+    mb, ma = _model_ptr(model_b), _model_ptr(model_a)
     _require_device(keys, xbar, ybar, hist, counters)
     dev = keys.device
     if xbar is None:
@@ -156,7 +182,7 @@ def partition_learned(keys, n, m, p_a, p_b, model_b, model_a, step0_a=1, step0_b
     if counters is None:
         counters = torch.zeros(4, dtype=torch.uint64, device=dev)
     _check(_lib.stable_merge_partition_learned(_ptr(keys), n, m, p_a, p_b, _dtype_code(keys),
-                                               _ptr(model_b), _ptr(model_a), int(step0_a),
+                                               mb, ma, int(step0_a),
                                                int(step0_b), int(window), _ptr(xbar), _ptr(ybar),
                                                _ptr(hist), _ptr(counters), _stream_ptr(stream)))
     return xbar, ybar, hist, counters
@@ -169,8 +195,7 @@ def merge_learned(keys, n, m, model_b, model_a, step0_a=1, step0_b=1, block=16, 
     ranks at blocks of `block` elements per side.  Returns (out_keys,
     out_payloads, hist, counters); the output is the unique stable merge
     whatever the models predict."""
-    _f32_params(model_b)
-    _f32_params(model_a)
+    mb, ma = _model_ptr(model_b), _model_ptr(model_a)
     _require_device(keys, payloads, out_keys, out_payloads, hist, counters, workspace)
     dev = keys.device
     code = _dtype_code(keys)
@@ -189,7 +214,7 @@ def merge_learned(keys, n, m, model_b, model_a, step0_a=1, step0_b=1, block=16, 
     if counters is None:
         counters = torch.zeros(4, dtype=torch.uint64, device=dev)
     _check(_lib.stable_merge_learned(_ptr(keys), _ptr(payloads), n, m, _ptr(out_keys),
-                                     _ptr(out_payloads), code, _ptr(model_b), _ptr(model_a),
+                                     _ptr(out_payloads), code, mb, ma,
                                      int(step0_a), int(step0_b), int(block), int(window),
                                      _ptr(hist), _ptr(counters), _ptr(workspace),
                                      workspace.numel(), _stream_ptr(stream)))
@@ -220,7 +245,7 @@ def sort_learned(keys, model, step_frac, payloads=None, *, out_keys=None, out_pa
     Returns (out_keys, out_payloads, counters) with counters = [searches,
     probes] accumulated over the passes; the output equals sort()'s."""
     from . import _opts
-    _f32_params(model)
+    mp = _model_ptr(model)
     _require_device(keys, payloads, out_keys, out_payloads, counters, workspace)
     N = keys.numel()
     code = _dtype_code(keys)
@@ -237,8 +262,81 @@ def sort_learned(keys, model, step_frac, payloads=None, *, out_keys=None, out_pa
                                                           ctypes.byref(o)))
         workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=dev)
     _check(_lib.stable_merge_sort_learned(_ptr(keys), _ptr(payloads), N, _ptr(out_keys),
-                                          _ptr(out_payloads), code, _ptr(model),
+                                          _ptr(out_payloads), code, mp,
                                           float(step_frac), _ptr(counters), _ptr(workspace),
                                           workspace.numel(), ctypes.byref(o),
                                           _stream_ptr(stream)))
     return out_keys, out_payloads, counters
+
+
+class Predictor:
+    """A rank-model handle of the library (sm_predictor_*): the network with
+    its key type and rank kind, trainable, savable to SM_PREDICTOR_BLOB_BYTES
+    host bytes and loadable from them.  ``params()`` is a device tensor view
+    of its 97 parameters for the calls that take a model."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def create(cls, dtype, is_high: bool) -> "Predictor":
+        h = ctypes.c_void_p()
+        code = _dtype_code(torch.empty(0, dtype=dtype))
+        _check(_lib.sm_predictor_create(ctypes.byref(h), code, int(bool(is_high))))
+        return cls(h)
+
+    @classmethod
+    def load(cls, blob: bytes) -> "Predictor":
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = ctypes.c_void_p()
+        _check(_lib.sm_predictor_load(ctypes.byref(h), buf, len(blob)))
+        return cls(h)
+
+    def train(self, X, Q, samples=1 << 20, steps=1000, lr=3e-3, seed=0, *, workspace=None,
+              stream=None) -> "Predictor":
+        _require_device(X, Q, workspace)
+        if workspace is None:
+            need = int(_lib.sm_rank_model_workspace_bytes(samples, _dtype_code(X)))
+            workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
+        _check(_lib.sm_predictor_train(self._h, _ptr(X), X.numel(), _ptr(Q), Q.numel(),
+                                       int(samples), int(steps), float(lr),
+                                       int(seed) & (2 ** 64 - 1), _ptr(workspace),
+                                       workspace.numel(), _stream_ptr(stream)))
+        return self
+
+    def info(self):
+        """(dtype code, is_high, trained array length, last loss)."""
+        d, h, n, loss = _i32(), _i32(), _i64(), _f32()
+        _check(_lib.sm_predictor_info(self._h, ctypes.byref(d), ctypes.byref(h), ctypes.byref(n),
+                                      ctypes.byref(loss)))
+        return d.value, bool(h.value), n.value, loss.value
+
+    def save(self) -> bytes:
+        buf = ctypes.create_string_buffer(BLOB_BYTES)
+        _check(_lib.sm_predictor_save(self._h, buf, BLOB_BYTES))
+        return buf.raw
+
+    def params(self) -> torch.Tensor:
+        """A copy of the handle's 97 parameters as a device float32 tensor
+        (the calls that take a model also accept the Predictor itself)."""
+        import numpy as np
+        p = np.frombuffer(self.save(), dtype="<f4", count=NPARAM, offset=40)
+        return torch.from_numpy(p.copy()).to(torch.device("cuda", torch.cuda.current_device()))
+
+    def ptr(self) -> ctypes.c_void_p:
+        """Device address of the handle's parameters."""
+        ptr = _lib.sm_predictor_params(self._h) if self._h else None
+        if not ptr:
+            raise SMError(-1, "invalid predictor handle")
+        return ctypes.c_void_p(ptr)
+
+    def close(self):
+        if self._h:
+            _check(_lib.sm_predictor_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -211,3 +211,80 @@ def test_reserved_options_rejected(sm):
     assert sm._lib.stable_merge_sort(0x10000, None, 100, 0x20000, None, 1, 0x30000, 1 << 20,
                                      ctypes.byref(o), None) == -1
     assert sm.workspace_bytes(10, 10, torch.uint32) > 0
+
+
+def test_workspace_alias_rejected(sm):
+    """A workspace that shares bytes with keys, payloads, outputs, the pair
+    descriptors or the cross ranks is rejected before any launch."""
+    # stable_merge: 20 uint32 keys at 0x10000, outputs at 0x20000
+    assert call_merge(sm, ws=0x10000) == -3                       # on the keys
+    assert call_merge(sm, ws=0x20000 - 256) == -3                 # runs into the outputs
+    assert call_merge(sm, pay=0x40000, opay=0x50000, ws=0x40000) == -3
+    assert call_merge(sm, pay=0x40000, opay=0x50000, ws=0x50000) == -3
+    assert call_merge(sm, ws=0x30000) != -3                       # separate: not an alias error
+    f = sm._lib.stable_merge_batched
+    o = sm.Options()
+
+    def batched(ws, offs=0x50000, na=0x60000):
+        return f(0x10000, None, offs, na, 4, 100, 0x20000, None, 1, ws, 1 << 20,
+                 ctypes.byref(o), None)
+    assert batched(0x10000) == -3
+    assert batched(0x30000, offs=0x30000 + 64) == -3              # offsets inside the workspace
+    assert batched(0x30000, na=0x30000 + 64) == -3
+    p = sm._lib.stable_merge_pieces
+    # xbar / ybar inside the workspace
+    assert p(0x10000, None, 10, 10, 2, 2, 0x30000, 0x31000, 0x20000, None, 1, 0x30000,
+             1 << 20, None) == -3
+    assert b"workspace overlaps" in sm._lib.sm_last_error()
+
+
+def _fnv1a(b: bytes) -> int:
+    """FNV-1a, 32 bits (offset basis 2166136261, prime 16777619)."""
+    h = 2166136261
+    for x in b:
+        h = ((h ^ x) * 16777619) & 0xFFFFFFFF
+    return h
+
+
+def _blob(magic=0x4D524D53, version=1, dtype=1, is_high=0, feature=1, hidden=32, nparam=97,
+          loss=0.25, length=1000, params=None, checksum=None) -> bytes:
+    import struct
+    params = params if params is not None else [0.5] * 97
+    head = struct.pack("<IIiiiiifq", magic, version, dtype, is_high, feature, hidden, nparam,
+                       loss, length) + struct.pack("<97f", *params)
+    assert len(head) == 428
+    return head + struct.pack("<I", _fnv1a(head) if checksum is None else checksum)
+
+
+def test_predictor_blob_checks(sm):
+    """Loading rejects every malformed blob host-side, before touching the
+    GPU; the handle calls reject NULL handles."""
+    from paper_1202_6575_amd import learned  # noqa: F401  (sets the argument types)
+    lib = sm._lib
+    h = ctypes.c_void_p()
+
+    def load(b, size=None):
+        buf = ctypes.create_string_buffer(b, len(b))
+        return lib.sm_predictor_load(ctypes.byref(h), buf, len(b) if size is None else size)
+
+    assert lib.sm_predictor_load(None, None, 0) == -1
+    assert load(_blob(), size=431) == -1                  # short
+    assert load(_blob(magic=0x12345678)) == -1
+    assert load(_blob(version=2)) == -1
+    assert load(_blob(checksum=1)) == -1                  # corrupted
+    assert b"checksum" in lib.sm_last_error()
+    bad = bytearray(_blob())
+    bad[100] ^= 1                                          # a flipped parameter bit
+    assert load(bytes(bad)) == -1
+    assert load(_blob(dtype=6)) == -2
+    assert load(_blob(hidden=16)) == -1
+    assert load(_blob(nparam=49)) == -1
+    assert load(_blob(feature=2)) == -1
+    assert load(_blob(is_high=2)) == -1
+    assert load(_blob(length=-1)) == -1
+    assert h.value is None                                 # nothing was created
+    assert lib.sm_predictor_create(ctypes.byref(h), 9, 0) == -2
+    assert lib.sm_predictor_destroy(None) == 0
+    assert lib.sm_predictor_params(None) is None
+    assert lib.sm_predictor_save(None, ctypes.create_string_buffer(432), 432) == -1
+    assert lib.sm_predictor_info(None, None, None, None, None) == -1

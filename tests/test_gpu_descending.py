@@ -1,16 +1,16 @@
 """Descending order: merges and sorts from largest to smallest key.
 
-The expected result is the definition of a stable descending sort, taken
-from Python's sorted(..., reverse=True), which keeps equal keys in input
-order: for a merge of A and B that input is A followed by B, so ties put A
-first and keep each source's order.  Float keys are compared in IEEE 754
-totalOrder through the oracle's sign-and-magnitude map."""
+The expected result comes from the CPU oracle run on the reversed order
+(``descending=True``): its merge and sort are pinned on the CPU against
+Python's stable sorted(..., reverse=True), so ties put A first and keep each
+source's order.  Payloads are the element indices, so the payload output is
+the permutation itself."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from helpers import total_order_sequence, dev, flush, host, rand_sorted
-from oracle.mlp import unsigned_order
 
 pytestmark = pytest.mark.gpu
 
@@ -19,10 +19,18 @@ import paper_1202_6575_amd as sm  # noqa: E402
 DTYPES = [np.int32, np.uint32, np.uint64, np.int64, np.float32, np.float64]
 
 
-def stable_desc_perm(keys: np.ndarray) -> np.ndarray:
-    """Indices of a stable descending sort of keys."""
-    u = unsigned_order(keys).tolist()
-    return np.array(sorted(range(len(u)), key=u.__getitem__, reverse=True), dtype=np.int64)
+def oracle_merge_desc(keys: np.ndarray, n: int):
+    """(keys, index permutation) of the oracle's descending merge of
+    keys[:n] and keys[n:], payload = index."""
+    idx = np.arange(len(keys), dtype=np.uint32)
+    c, pc = oracle.merge(keys[:n], keys[n:], idx[:n], idx[n:], descending=True)
+    return c, pc
+
+
+def oracle_sort_desc(keys: np.ndarray):
+    """(keys, index permutation) of the oracle's descending stable sort."""
+    c, pc = oracle.sort(keys, np.arange(len(keys), dtype=np.uint32), descending=True)
+    return c, pc
 
 
 def same_bits(a: np.ndarray, b: np.ndarray) -> bool:
@@ -46,10 +54,10 @@ def test_merge_descending(dtype, with_pay):
             ck, cp = sm.merge(dev(keys), n, m, None if pay is None else dev(pay),
                               descending=True, validate=True)
             torch.cuda.synchronize()
-            perm = stable_desc_perm(keys)
-            assert same_bits(host(ck), keys[perm])
+            rk, rp = oracle_merge_desc(keys, n)
+            assert same_bits(host(ck), rk)
             if with_pay:
-                assert np.array_equal(host(cp), perm.astype(np.uint32))
+                assert np.array_equal(host(cp), rp)
 
 
 def test_merge_descending_inputs_untouched_and_tiles():
@@ -59,14 +67,14 @@ def test_merge_descending_inputs_untouched_and_tiles():
     A, B = desc_sorted(g, 30_000, 100, np.int32), desc_sorted(g, 20_011, 100, np.int32)
     keys = np.concatenate([A, B])
     dk = dev(keys)
-    perm = stable_desc_perm(keys)
+    rk, rp = oracle_merge_desc(keys, len(A))
     for kw in ({}, {"tile": 64}, {"p_a": 7, "p_b": 3}):
         flush(f"merge descending options {kw}")
         ck, cp = sm.merge(dk, len(A), len(B), dev(np.arange(len(keys), dtype=np.uint32)),
                           descending=True, **kw)
         torch.cuda.synchronize()
-        assert np.array_equal(host(ck), keys[perm])
-        assert np.array_equal(host(cp), perm.astype(np.uint32))
+        assert np.array_equal(host(ck), rk)
+        assert np.array_equal(host(cp), rp)
         assert np.array_equal(host(dk), keys)
     asc = np.concatenate([A[::-1], B[::-1]])
     with pytest.raises(sm.SMError):
@@ -85,9 +93,9 @@ def test_merge_descending_small_blocks(dtype):
         ck, cp = sm.merge(dev(keys), n, m, dev(np.arange(n + m, dtype=np.uint32)),
                           p_a=p, p_b=p, descending=True)
         torch.cuda.synchronize()
-        perm = stable_desc_perm(keys)
-        assert same_bits(host(ck), keys[perm])
-        assert np.array_equal(host(cp), perm.astype(np.uint32))
+        rk, rp = oracle_merge_desc(keys, n)
+        assert same_bits(host(ck), rk)
+        assert np.array_equal(host(cp), rp)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -108,9 +116,9 @@ def test_batched_descending(dtype):
     ck, cp = host(ck), host(cp)
     for k in range(len(sizes)):
         lo, hi = offs[k], offs[k + 1]
-        perm = lo + stable_desc_perm(keys[lo:hi])
-        assert same_bits(ck[lo:hi], keys[perm])
-        assert np.array_equal(cp[lo:hi], perm.astype(np.uint32))
+        rk, rp = oracle_merge_desc(keys[lo:hi], n_a[k])
+        assert same_bits(ck[lo:hi], rk)
+        assert np.array_equal(cp[lo:hi], rp + np.uint32(lo))
 
 
 def rand_keys(g, N, alphabet, dtype):
@@ -128,23 +136,23 @@ def test_sort_descending(dtype, with_pay):
             flush(f"sort descending {np.dtype(dtype).name} pay={with_pay} N={N} alpha={alpha}")
             ck, cp = sm.sort(dev(keys), None if pay is None else dev(pay), descending=True)
             torch.cuda.synchronize()
-            perm = stable_desc_perm(keys)
-            assert same_bits(host(ck), keys[perm])
+            rk, rp = oracle_sort_desc(keys)
+            assert same_bits(host(ck), rk)
             if with_pay:
-                assert np.array_equal(host(cp), perm.astype(np.uint32))
+                assert np.array_equal(host(cp), rp)
 
 
 def test_sort_descending_in_place_and_runs():
     g = np.random.default_rng(55)
     keys = rand_keys(g, 100_003, 200, np.uint64)
-    perm = stable_desc_perm(keys)
+    rk, rp = oracle_sort_desc(keys)
     for run in (256, 2048):
         flush(f"sort descending in place run={run}")
         dk, dp = dev(keys), dev(np.arange(len(keys), dtype=np.uint32))
         sm.sort(dk, dp, out_keys=dk, out_payloads=dp, run=run, descending=True)
         torch.cuda.synchronize()
-        assert np.array_equal(host(dk), keys[perm])
-        assert np.array_equal(host(dp), perm.astype(np.uint32))
+        assert np.array_equal(host(dk), rk)
+        assert np.array_equal(host(dp), rp)
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
@@ -157,14 +165,14 @@ def test_float_specials_descending(dt):
     flush(f"float specials descending {np.dtype(dt).name}")
     ck, cp = sm.sort(dev(keys), dev(np.arange(len(keys), dtype=np.uint32)), descending=True)
     torch.cuda.synchronize()
-    perm = stable_desc_perm(keys)
-    assert same_bits(host(ck), keys[perm])
-    assert np.array_equal(host(cp), perm.astype(np.uint32))
-    A, B = keys[:12_000][stable_desc_perm(keys[:12_000])], keys[12_000:][stable_desc_perm(keys[12_000:])]
+    rk, rp = oracle_sort_desc(keys)
+    assert same_bits(host(ck), rk)
+    assert np.array_equal(host(cp), rp)
+    A, B = oracle_sort_desc(keys[:12_000])[0], oracle_sort_desc(keys[12_000:])[0]
     both = np.concatenate([A, B])
     mk, _ = sm.merge(dev(both), len(A), len(B), descending=True, validate=True)
     torch.cuda.synchronize()
-    assert same_bits(host(mk), both[stable_desc_perm(both)])
+    assert same_bits(host(mk), oracle_merge_desc(both, len(A))[0])
 
 
 def test_segmented_descending():
@@ -181,6 +189,6 @@ def test_segmented_descending():
         ck, cp = host(ck), host(cp)
         for s in range(len(lengths)):
             lo, hi = int(offs[s]), int(offs[s + 1])
-            perm = lo + stable_desc_perm(keys[lo:hi])
-            assert same_bits(ck[lo:hi], keys[perm])
-            assert np.array_equal(cp[lo:hi], perm.astype(np.uint32))
+            rk, rp = oracle_sort_desc(keys[lo:hi])
+            assert same_bits(ck[lo:hi], rk)
+            assert np.array_equal(cp[lo:hi], rp + np.uint32(lo))

@@ -256,3 +256,45 @@ def test_trained_network_gain():
     assert learned_probes < plain_probes - 3
     xr, yr = oracle.cross_ranks(A, B, p_a, p_b)
     assert np.array_equal(host(xb), xr) and np.array_equal(host(yb), yr)
+
+
+def test_predictor_save_load_round_trip():
+    """A trained handle saved to host bytes and loaded again holds the same
+    parameters and metadata, and the whole learned merge through either
+    handle writes the same bytes (and the same histogram and counters) --
+    the oracle's merge."""
+    g = np.random.default_rng(91)
+    n, m = 300_001, 200_003
+    A, B = rand_sorted(g, n, 1 << 24, np.uint32), rand_sorted(g, m, 1 << 24, np.uint32)
+    keys = dev(np.concatenate([A, B]))
+    flush("predictor create / train / save / load")
+    pb = learned.Predictor.create(torch.uint32, False).train(keys[n:], keys[:n], samples=1 << 14,
+                                                             steps=200, seed=3)
+    pa = learned.Predictor.create(torch.uint32, True).train(keys[:n], keys[n:], samples=1 << 14,
+                                                            steps=200, seed=4)
+    blob_b, blob_a = pb.save(), pa.save()
+    assert len(blob_b) == learned.BLOB_BYTES == 432
+    lb, la = learned.Predictor.load(blob_b), learned.Predictor.load(blob_a)
+    assert lb.save() == blob_b and la.save() == blob_a
+    assert torch.equal(lb.params(), pb.params()) and torch.equal(la.params(), pa.params())
+    ib, il = pb.info(), lb.info()
+    assert ib == il and ib[0] == 1 and ib[1] is False and ib[2] == m and ib[3] < 1.0
+    assert la.info()[1] is True and la.info()[2] == n
+    s0a = learned.step0_from_loss(ib[3], m)
+    s0b = learned.step0_from_loss(la.info()[3], n)
+    outs = []
+    for mb, ma in ((pb, pa), (lb, la)):
+        ok, _, h, c = learned.merge_learned(keys, n, m, mb, ma, s0a, s0b, block=16, window=1 << 12)
+        torch.cuda.synchronize()
+        outs.append((host(ok), host(h), host(c)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+    ref, _ = oracle.merge(A, B)
+    assert np.array_equal(outs[0][0], ref)
+    # the loaded handle outlives the one it came from
+    pb.close()
+    ok, _, _, _ = learned.merge_learned(keys, n, m, lb, la, s0a, s0b, block=16, window=1 << 12)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ok), ref)
+    for h in (pa, lb, la):
+        h.close()

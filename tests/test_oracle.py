@@ -14,6 +14,7 @@ Nothing here compares the oracle with itself.  The pins are:
 """
 import itertools
 import json
+import math
 import os
 
 import numpy as np
@@ -358,6 +359,62 @@ def test_sort_dtypes(dtype):
 # O6: bounded exponential search
 # --------------------------------------------------------------------------
 
+# --------------------------------------------------------------------------
+# Descending order: the same routines on the reversed order relation
+# --------------------------------------------------------------------------
+
+def _desc_index(keys: np.ndarray) -> np.ndarray:
+    """Indices of a stable descending sort, by Python's sorted(reverse=True),
+    which keeps equal keys in input order; keys compared in their type's
+    order (floats here are finite and nonzero-signed, so numeric order)."""
+    vals = keys.tolist()
+    return np.array(sorted(range(len(vals)), key=vals.__getitem__, reverse=True), dtype=np.int64)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_descending_merge_and_sort_brute_force(dtype):
+    """With descending=True the merge of two non-increasing arrays is the
+    stable descending sort of A || B (ties: A first, each source in order),
+    and the sort is the stable descending sort of its input."""
+    g = np.random.default_rng(71)
+    for _ in range(150):
+        n, m = int(g.integers(0, 60)), int(g.integers(0, 60))
+        alpha = int(g.integers(1, 12))
+        A = rand_sorted(g, n, alpha, dtype)[::-1].copy()
+        B = rand_sorted(g, m, alpha, dtype)[::-1].copy()
+        cat = np.concatenate([A, B])
+        idx = _desc_index(cat)
+        pa = np.arange(n, dtype=np.uint32)
+        pb = np.arange(n, n + m, dtype=np.uint32)
+        c, pc = oracle.merge(A, B, pa, pb, descending=True)
+        assert np.array_equal(c, cat[idx]) and np.array_equal(pc, idx.astype(np.uint32))
+        p_a, p_b = int(g.integers(1, 9)), int(g.integers(1, 9))
+        c2, pc2 = oracle.merge_by_pieces(A, B, p_a, p_b, pa, pb, descending=True)
+        assert np.array_equal(c2, c) and np.array_equal(pc2, pc)
+        shuffled = g.permutation(cat)
+        run = int(g.integers(1, 9))
+        sk, sp = oracle.sort(shuffled, np.arange(len(cat), dtype=np.uint32), run, descending=True)
+        sidx = _desc_index(shuffled)
+        assert np.array_equal(sk, shuffled[sidx]) and np.array_equal(sp, sidx.astype(np.uint32))
+
+
+def test_descending_ranks_counting_definition():
+    """In non-increasing order, rank_low(x, X) counts the elements strictly
+    greater than x and rank_high(x, X) those greater than or equal to x."""
+    g = np.random.default_rng(72)
+    for _ in range(300):
+        X = np.sort(g.integers(-20, 20, size=int(g.integers(0, 40))).astype(np.int32))[::-1].copy()
+        x = int(g.integers(-25, 25))
+        assert oracle.rank_low(x, X, descending=True) == int((X > x).sum())
+        assert oracle.rank_high(x, X, descending=True) == int((X >= x).sum())
+    A = np.array([9, 7, 7, 3], dtype=np.int32)
+    B = np.array([8, 7, 1], dtype=np.int32)
+    xbar, ybar = oracle.cross_ranks(A, B, 2, 3, descending=True)
+    # A blocks start at 9 and 7: 0 and 1 elements of B come strictly before;
+    # B blocks start at 8, 7, 1: 1, 3 and 4 elements of A come at or before
+    assert list(xbar) == [0, 1, 3] and list(ybar) == [1, 3, 4, 4]
+
+
 @pytest.mark.parametrize("is_high", [False, True])
 def test_gallop_exact(is_high):
     g = np.random.default_rng(12)
@@ -472,6 +529,81 @@ def test_adam_first_step_closed_form():
     p1, m, v = mlp.adam_step(p0, g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(p1, p0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_three_steps_from_nonzero_moments():
+    """Three Adam updates (Kingma and Ba, 2015: m_t = b1 m_{t-1} + (1 - b1) g_t,
+    v_t = b2 v_{t-1} + (1 - b2) g_t^2, p_t = p_{t-1} - lr mhat_t / (sqrt(vhat_t)
+    + eps) with mhat_t = m_t / (1 - b1^t), vhat_t = v_t / (1 - b2^t)) from
+    m_0 = 2, v_0 = 8, p_0 = 0 with b1 = 3/4, b2 = 7/8, lr = 1, eps = 0 and
+    gradients 4, 0, -4 at t = 1, 2, 3.  Worked by hand in fractions:
+      t=1: m = 3/2 + 1 = 5/2,  v = 7 + 2 = 9,         mhat = 10,    vhat = 72
+      t=2: m = 15/8,           v = 63/8,              mhat = 30/7,  vhat = 168/5
+      t=3: m = 45/32 - 1 = 13/32, v = 441/64 + 2 = 569/64,
+           mhat = (13/32) / (37/64) = 26/37,  vhat = (569/64) / (169/512) = 4552/169
+    Neither b1 nor b2 is 1/2, so exchanging b and 1 - b in either moment, a
+    missing bias correction or a power t - 1 in it changes the result."""
+    p3_expected = -(10 / math.sqrt(72)) - (30 / 7) / math.sqrt(168 / 5) \
+        - (26 / 37) / math.sqrt(4552 / 169)
+    p = np.array([0.0])
+    m = np.array([2.0])
+    v = np.array([8.0])
+    seen = []
+    for t, g in ((1, 4.0), (2, 0.0), (3, -4.0)):
+        p, m, v = mlp.adam_step(p, np.array([g]), m, v, t, 1.0, beta1=0.75, beta2=0.875, eps=0.0)
+        seen.append((float(p[0]), float(m[0]), float(v[0])))
+    assert seen[0][1] == 2.5 and seen[0][2] == 9.0
+    assert abs(seen[0][0] - (-10 / math.sqrt(72))) < 1e-14
+    assert seen[1][1] == 15 / 8 and seen[1][2] == 63 / 8
+    assert seen[2][1] == 13 / 32 and seen[2][2] == 569 / 64
+    assert abs(seen[2][0] - p3_expected) < 1e-13
+    # eps is added to the square root, not under it: with vhat = 72 and
+    # eps = 1, the first step is 10 / (sqrt(72) + 1)
+    p1, _, _ = mlp.adam_step(np.array([0.0]), np.array([4.0]), np.array([2.0]), np.array([8.0]),
+                             1, 1.0, beta1=0.75, beta2=0.875, eps=1.0)
+    assert abs(float(p1[0]) + 10 / (math.sqrt(72) + 1)) < 1e-14
+
+
+def _constant_net(b2: float) -> np.ndarray:
+    """A network whose output is b2 for every key (first layer and output
+    weights zero)."""
+    p = np.zeros(mlp.NPARAM)
+    p[96] = b2
+    return p
+
+
+def test_predict_rank_rounding_and_clamps():
+    """predict_rank = y * len rounded half to even, clamped to [0, len], NaN
+    -> 0 (the GPU predictor returns 0 for a non-number as well).  len = 8:
+    y = 5/16 -> 2.5 -> 2, 7/16 -> 3.5 -> 4, 3/16 -> 1.5 -> 2, 9/16 -> 4.5 -> 4;
+    y < 0 -> 0; y * len > len -> len; +inf -> len, -inf and NaN -> 0."""
+    keys = np.array([0, 7, 2 ** 32 - 1], dtype=np.uint32)
+    cases = [(5 / 16, 2), (7 / 16, 4), (3 / 16, 2), (9 / 16, 4), (0.0, 0), (1.0, 8),
+             (-0.25, 0), (1.25, 8), (math.inf, 8), (-math.inf, 0), (math.nan, 0)]
+    for b2, want in cases:
+        with np.errstate(invalid="ignore"):
+            got = mlp.predict_rank(_constant_net(b2), keys, 8)
+        assert got.dtype == np.int64
+        assert list(got) == [want] * 3, (b2, got)
+    # an empty target array: every prediction is 0
+    assert list(mlp.predict_rank(_constant_net(0.7), keys, 0)) == [0, 0, 0]
+
+
+def test_predict_rank_through_hidden_unit():
+    """One hidden unit h = ReLU(phi - 1/2) with output 1/4 + 2 h.  uint32 keys:
+    phi(0) = 0 -> y = 1/4; phi(2^24 - 1) = log2(2^24) / 32 = 3/4 -> y = 3/4;
+    phi(2^32 - 1) = 1 -> y = 5/4.  With len = 8: 2, 6 and 8 (clamped)."""
+    p = np.zeros(mlp.NPARAM)
+    p[0] = 1.0       # W1[0]
+    p[32] = -0.5     # b1[0]
+    p[64] = 2.0      # w2[0]
+    p[96] = 0.25     # b2
+    keys = np.array([0, 2 ** 24 - 1, 2 ** 32 - 1], dtype=np.uint32)
+    assert list(mlp.predict_rank(p, keys, 8)) == [2, 6, 8]
+    # a negative W1 turns the unit off above the knot: h = ReLU(1/2 - phi)
+    # gives y = 5/4 (clamped to 8), 1/4 and 1/4
+    p[0], p[32] = -1.0, 0.5
+    assert list(mlp.predict_rank(p, keys, 8)) == [8, 2, 2]
 
 
 def test_mlp_init_interpolates_knots():
