@@ -131,6 +131,31 @@ SM_API int stable_merge(const void *keys, const uint32_t *payloads, int64_t n, i
                  void *ws, size_t ws_bytes, const sm_options *opt, void *stream);
 
 /*
+ * Addition for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * stable_merge without a workspace argument.  Same arguments, result and
+ * errors as stable_merge, minus ws / ws_bytes.  Its cross ranks and
+ * subproblem descriptors live in a fixed scratch array of
+ * SM_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on, from its first call there until the process ends.  The call
+ * allocates nothing (no hipMalloc, no hipFree, no allocating library call).
+ *   - A merge whose stable_merge_workspace_bytes() exceeds the limit returns
+ *     SM_ERR_WORKSPACE before any launch (use stable_merge, or a larger
+ *     tile).  The default tile needs about 9.1 MB for n = m = 2^28.
+ *   - opt->validate is rejected (SM_ERR_ARG): it needs a host read-back.
+ *   - Every call on one device shares that device's scratch array, and the
+ *     array keeps the last call's contents (nothing in it has to start at
+ *     zero).  Calls that overlap on one device -- on two streams, or from
+ *     two host threads without ordering -- race on it and give undefined
+ *     results; calls ordered on one stream are safe.
+ *   - The device is the current HIP device; stream must belong to it.
+ */
+#define SM_NOALLOC_SCRATCH_BYTES (16u << 20)
+SM_API int stable_merge_noalloc(const void *keys, const uint32_t *payloads, int64_t n, int64_t m,
+                 void *out_keys, uint32_t *out_payloads, int dtype,
+                 const sm_options *opt, void *stream);
+
+/*
  * Steps 1 and 2 alone (Section 2): xbar[i] = rank_low(A[x_i], B) for
  * 0 <= i < p_a with xbar[p_a] = m, and ybar[j] = rank_high(B[y_j], A) for
  * 0 <= j < p_b with ybar[p_b] = n, where x_i and y_j are the block starts of

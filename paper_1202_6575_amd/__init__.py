@@ -22,7 +22,7 @@ import os
 
 import torch
 
-__all__ = ["merge", "partition", "merge_pieces", "merge_batched", "sort", "segmented_sort",
+__all__ = ["merge", "merge_noalloc", "partition", "merge_pieces", "merge_batched", "sort", "segmented_sort",
            "workspace_bytes", "pieces_workspace_bytes", "batched_workspace_bytes",
            "sort_workspace_bytes", "segmented_sort_workspace_bytes", "SMError", "LIB_PATH",
            "DTYPES"]
@@ -65,6 +65,9 @@ _lib.stable_merge_workspace_bytes.argtypes = [_i64, _i64, _i32, _i32, ctypes.POI
 _lib.stable_merge.restype = _i32
 _lib.stable_merge.argtypes = [_vp, _vp, _i64, _i64, _vp, _vp, _i32, _vp, _sz,
                               ctypes.POINTER(Options), _vp]
+_lib.stable_merge_noalloc.restype = _i32
+_lib.stable_merge_noalloc.argtypes = [_vp, _vp, _i64, _i64, _vp, _vp, _i32,
+                                      ctypes.POINTER(Options), _vp]
 _lib.stable_merge_pieces.restype = _i32
 _lib.stable_merge_pieces.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32,
                                      _vp, _sz, _vp]
@@ -182,6 +185,29 @@ def merge(keys: torch.Tensor, n: int, m: int | None = None, payloads: torch.Tens
     _check(_lib.stable_merge(_ptr(keys), _ptr(payloads), n, m, _ptr(out_keys), _ptr(out_payloads),
                              code, _ptr(workspace), workspace.numel(), ctypes.byref(o),
                              _stream_ptr(stream)))
+    return out_keys, out_payloads
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def merge_noalloc(keys: torch.Tensor, n: int, m: int | None, payloads: torch.Tensor | None,
+                  out_keys: torch.Tensor, out_payloads: torch.Tensor | None = None, *,
+                  p_a: int = 0, p_b: int = 0, tile: int = 0, descending: bool = False,
+                  stream=None):
+    """stable_merge_noalloc: the merge of ``merge`` into caller-given outputs,
+    with the library's per-device scratch array in place of a workspace (for
+    callers that cannot allocate).  Calls that overlap on one device race on
+    that array."""
+    if m is None:
+        m = keys.numel() - n
+    if keys.numel() < n + m or out_keys.numel() < n + m:
+        raise SMError(-1, "keys and out_keys must hold n + m elements")
+    _require_device(keys, payloads, out_keys, out_payloads)
+    o = _opts(p_a, p_b, tile, False, descending=descending)
+    _check(_lib.stable_merge_noalloc(_ptr(keys), _ptr(payloads), n, m, _ptr(out_keys),
+                                     _ptr(out_payloads), _dtype_code(keys), ctypes.byref(o),
+                                     _stream_ptr(stream)))
     return out_keys, out_payloads
 
 

@@ -14,6 +14,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "stablemerge.h"
@@ -220,6 +221,68 @@ int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t*
     return SM_OK;
 }
 
+// Steps 1-4 of one merge once its plan and buffers have been checked; `w`
+// is device memory of at least pl.ws_bytes bytes, in any state (every
+// kernel writes what it later reads).
+int merge_run(const Plan& pl, const void* keys, const uint32_t* payloads, int64_t n, int64_t m,
+              void* out_keys, uint32_t* out_payloads, int dtype, char* w, const sm_options* opt,
+              hipStream_t st) {
+    int64_t* xbar = reinterpret_cast<int64_t*>(w);
+    int64_t* ybar = xbar + (pl.p_a + 1);
+    int* flag = reinterpret_cast<int*>(w + pl.off_flag);
+    hipError_t e;
+
+    const int kd = kernel_dtype(dtype, opt);
+    if (opt && opt->validate) {
+        int host_flag = 0;
+        e = sm::launch_clear(flag, 1, st);
+        if (e == hipSuccess) e = sm::launch_validate(kd, keys, n, m, flag, st);
+        if (e != hipSuccess) return hip_fail(e, "validate launch");
+        e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "validate readback");
+        if (host_flag) return fail(SM_ERR_UNSORTED, "A or B is not sorted in the requested order");
+    }
+
+    e = sm::launch_partition(kd, keys, n, m, pl.p_a, pl.p_b, xbar, ybar, st);
+    if (e != hipSuccess) return hip_fail(e, "partition launch");
+    return cases_and_merge(pl, kd, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
+                           w + pl.off_desc, st);
+}
+
+// The scratch memory of stable_merge_noalloc: one copy per device, held from
+// the library's first use on that device until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: every
+// host use goes through the device address that hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+}  // namespace
+
+static __device__ __align__(256) char scratch[SM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SM_ERR_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255))
+            return fail(SM_ERR_HIP, "scratch address is null or misaligned");
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -304,30 +367,36 @@ int stable_merge(const void* keys, const uint32_t* payloads, int64_t n, int64_t 
     if (rc != SM_OK) return rc;
     rc = check_ws_alias(ws, pl.ws_bytes, keys, payloads, total, out_keys, out_payloads, dtype);
     if (rc != SM_OK) return rc;
+    return merge_run(pl, keys, payloads, n, m, out_keys, out_payloads, dtype,
+                     static_cast<char*>(ws), opt, static_cast<hipStream_t>(stream));
+}
 
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    char* w = static_cast<char*>(ws);
-    int64_t* xbar = reinterpret_cast<int64_t*>(w);
-    int64_t* ybar = xbar + (pl.p_a + 1);
-    int* flag = reinterpret_cast<int*>(w + pl.off_flag);
-    hipError_t e;
-
-    const int kd = kernel_dtype(dtype, opt);
-    if (opt && opt->validate) {
-        int host_flag = 0;
-        e = sm::launch_clear(flag, 1, st);
-        if (e == hipSuccess) e = sm::launch_validate(kd, keys, n, m, flag, st);
-        if (e != hipSuccess) return hip_fail(e, "validate launch");
-        e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "validate readback");
-        if (host_flag) return fail(SM_ERR_UNSORTED, "A or B is not sorted in the requested order");
-    }
-
-    e = sm::launch_partition(kd, keys, n, m, pl.p_a, pl.p_b, xbar, ybar, st);
-    if (e != hipSuccess) return hip_fail(e, "partition launch");
-    return cases_and_merge(pl, kd, keys, payloads, n, m, xbar, ybar, out_keys, out_payloads,
-                           w + pl.off_desc, st);
+int stable_merge_noalloc(const void* keys, const uint32_t* payloads, int64_t n, int64_t m,
+                         void* out_keys, uint32_t* out_payloads, int dtype,
+                         const sm_options* opt, void* stream) {
+    const bool pay = payloads != nullptr;
+    if (!options_ok(opt)) return fail(SM_ERR_ARG, "sm_options.reserved must be zero");
+    if (opt && opt->validate)
+        return fail(SM_ERR_ARG, "validate reads a status word back to the host; "
+                                "stable_merge_noalloc does not offer it");
+    Plan pl;
+    int rc = make_plan(n, m, dtype, pay, opt ? opt->p_a : 0, opt ? opt->p_b : 0,
+                       pick_tile(dtype, pay, opt), &pl);
+    if (rc != SM_OK) return rc;
+    const int64_t total = n + m;
+    if (total == 0) return SM_OK;
+    rc = check_buffers(keys, payloads, total, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    if (pl.ws_bytes > (size_t)SM_NOALLOC_SCRATCH_BYTES)
+        return fail(SM_ERR_WORKSPACE,
+                    "this merge needs %zu bytes of scratch, above the built-in %zu; "
+                    "use stable_merge with a workspace, or a larger tile",
+                    pl.ws_bytes, (size_t)SM_NOALLOC_SCRATCH_BYTES);
+    char* w = nullptr;
+    rc = scratch_on_current_device(&w);
+    if (rc != SM_OK) return rc;
+    return merge_run(pl, keys, payloads, n, m, out_keys, out_payloads, dtype, w, opt,
+                     static_cast<hipStream_t>(stream));
 }
 
 size_t stable_merge_batched_workspace_bytes(int64_t count, int64_t total, int dtype,

@@ -288,3 +288,32 @@ def test_predictor_blob_checks(sm):
     assert lib.sm_predictor_params(None) is None
     assert lib.sm_predictor_save(None, ctypes.create_string_buffer(432), 432) == -1
     assert lib.sm_predictor_info(None, None, None, None, None) == -1
+
+
+def test_noalloc_error_paths(sm):
+    """stable_merge_noalloc rejects bad arguments, validate, and plans above
+    its scratch limit before it looks up the scratch array (no GPU call)."""
+    def call(keys=0x10000, pay=None, n=10, m=10, out=0x20000, opay=None, dtype=1, opts=None):
+        o = opts if opts is not None else sm.Options()
+        return sm._lib.stable_merge_noalloc(keys, pay, n, m, out, opay, dtype, ctypes.byref(o),
+                                            None)
+    assert call(dtype=9) == -2
+    assert call(n=-1) == -1
+    assert call(pay=0x40000) == -1
+    assert call(out=0x10000 + 16) == -3
+    assert call(n=0, m=0) == 0
+    o = sm.Options()
+    o.validate = 1
+    assert call(opts=o) == -1
+    o = sm.Options()
+    o.reserved[0] = 1
+    assert call(opts=o) == -1
+    # 2^21 + 2^21 blocks need 32 MiB of cross ranks alone
+    n = m = 1 << 21
+    o = sm.Options()
+    o.p_a, o.p_b = n, m
+    assert call(n=n, m=m, out=0x10000 + 64 * n, opts=o) == -4
+    assert b"scratch" in sm._lib.sm_last_error()
+    hdr = open(os.path.join(HEADER_DIR, "stablemerge.h")).read()
+    mt = re.search(r"#define SM_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert mt and sm.NOALLOC_SCRATCH_BYTES == int(mt.group(1)) << int(mt.group(2))
