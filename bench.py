@@ -40,11 +40,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PMC_FILE = os.path.join(ROOT, "profiles", "merge_kernel_uniform2x2e28_u32_pmc.json")
+TRACE_FILE = os.path.join(ROOT, "profiles", "merge_kernel_uniform2x2e28_u32_trace.json")
 KERNEL_SOURCES = ["paper_1202_6575_amd/csrc/sm_device.h", "paper_1202_6575_amd/csrc/sm_merge.hip"]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def host_info() -> dict:
+    """CPU model and core counts of the host the benchmark runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def cpu_threads() -> int:
+    """Worker threads for the multi-threaded oracle baselines: the cores this
+    process may run on, at most 16 (one GPU's share of its host)."""
+    return max(1, min(16, host_info()["usable_cores"]))
 
 
 def kernel_source_hash() -> str:
@@ -67,6 +92,27 @@ def traffic_from_profile(launch_bytes_alg: float):
     return pmc.get("hbm_bytes_per_launch")
 
 
+def trace_from_profile():
+    """Steady-state merge-kernel duration from a committed rocprofv3 kernel
+    trace of this benchmark, if it was taken on the current kernel source."""
+    if not os.path.exists(TRACE_FILE):
+        return None
+    with open(TRACE_FILE) as f:
+        tr = json.load(f)
+    if tr.get("source_hash") != kernel_source_hash():
+        return None
+    return tr
+
+
+def trace_summary(alg_bytes: float):
+    tr = trace_from_profile()
+    if tr is None:
+        return None
+    return {"source": os.path.relpath(TRACE_FILE, ROOT),
+            "steady_mean_ms": tr["steady_mean_ms"], "steady_dispatches": tr["steady_dispatches"],
+            "frac": round(alg_bytes / (tr["steady_mean_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 MERGE_KERNEL_TAG = "merge_pipelined_kernel"
 COPY_KERNEL_TAG = "bitwise_not"
 
@@ -85,6 +131,34 @@ def _pmc_per_dispatch(run_dir: str, counter: str):
             if key:
                 vals[key].append(float(r["Counter_Value"]))
     return {k: (sum(v) / len(v) if v else None) for k, v in vals.items()}
+
+
+def summarize_trace(trace_dir: str, warmup: int, out_path: str = TRACE_FILE):
+    """Per-dispatch durations of the merge kernel from a rocprofv3
+    --kernel-trace (csv) of this benchmark: the first `warmup` dispatches
+    (the untimed warm-up steps) are listed apart, the rest summarised."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if MERGE_KERNEL_TAG in r["Kernel_Name"]:
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    if len(rows) <= warmup:
+        raise SystemExit(f"{len(rows)} merge dispatches, warm-up {warmup}")
+    ms = [d * 1e-6 for _, d in rows]
+    steady = sorted(ms[warmup:])
+    out = {"kernel": "merge_pipelined_kernel<uint32, keys only>",
+           "source_hash": kernel_source_hash(),
+           "warmup_dispatches_ms": [round(x, 4) for x in ms[:warmup]],
+           "steady_dispatches": len(steady),
+           "steady_mean_ms": round(sum(steady) / len(steady), 4),
+           "steady_median_ms": round(steady[len(steady) // 2], 4),
+           "steady_min_ms": round(steady[0], 4), "steady_max_ms": round(steady[-1], 4)}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, log2n: int, out_path: str = PMC_FILE):
@@ -132,7 +206,12 @@ def main():
                     help="batched pairs: totals log-uniform in [16, 2^this]")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--pmc-out", default=PMC_FILE)
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
+    ap.add_argument("--trace-out", default=TRACE_FILE)
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.warmup, args.trace_out)
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.log2n, args.pmc_out)
         return
@@ -224,7 +303,7 @@ def main():
         oracle.merge(A, B)
         dt = time.perf_counter() - t
         cpu = {"value": round((n + m) / dt / 1e9, 4), "unit": "Gelem/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "host": host_info(),
                "sample": f"the full workload once: oracle two-pointer merge of the same "
                          f"n=m=2^{args.log2n} uint32 arrays in host memory, {dt:.2f} s"}
 
@@ -251,7 +330,13 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile(alg_bytes),
                      "kernel": "merge_pipelined_kernel<uint32, keys only>",
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "timing": "HIP events on the launch stream around stable_merge_pieces "
+                               "(the cases kernel, about 5 us, then the merge kernel), mean "
+                               "over the timed steps",
+                     "frac_whole_step": round(alg_bytes / (ms_per_step * 1e-3) / 1e9
+                                              / HBM_PEAK_GBS, 4),
+                     "trace": trace_summary(alg_bytes)},
         "cpu_baseline": cpu,
         "copy_reference": {"GB/s": round(alg_bytes / (copy_ms * 1e-3) / 1e9, 1),
                            "ms": round(copy_ms, 4),
@@ -394,6 +479,7 @@ def bench_batched(args, plain_gelems, log2max):
     per_pair()
     pp_ms = _events_ms(per_pair, 2, stream)
     pp_gel = float(lens.sum()) / (pp_ms * 1e-3) / 1e9
+    cpu = None if args.no_cpu_baseline else batched_cpu_baseline(keys, off_h, na_h)
     return {"workload": f"{count} pairs, L_k = floor(2^U), U ~ U[4, {log2max}], "
                         f"m_k = floor(f L_k), int32 keys uniform in [0, 2^20), keys only",
             "total_elements": total, "Gelem/s": round(gel, 2), "ms": round(graph_ms, 4),
@@ -406,7 +492,41 @@ def bench_batched(args, plain_gelems, log2max):
                          "frac": round(alg / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "per_pair_calls": {"pairs_sampled": len(sample), "Gelem/s": round(pp_gel, 3),
                                "speedup_of_batched": round(gel / pp_gel, 1)},
+            "cpu_baseline": cpu,
             "vs_plain_merge_Gelem/s": round(gel / plain_gelems, 3)}
+
+
+def batched_cpu_baseline(keys, off_h, na_h, budget: int = 1 << 28):
+    """The oracle's batched merge (its two-pointer merge applied pair by
+    pair, in C) on the leading pairs of the batch (pairs are drawn
+    independently, so a prefix is a sample of the whole), at most `budget`
+    elements, split into contiguous ranges of pairs over host threads (the
+    oracle's C routine runs without Python's lock)."""
+    import concurrent.futures
+    import numpy as np
+    import oracle
+    k = int(np.searchsorted(off_h, budget, side="right")) - 1
+    k = max(1, min(k, len(na_h)))
+    elems = int(off_h[k])
+    host = keys[:elems].cpu().numpy()
+    out = np.empty_like(host)
+    offs = np.ascontiguousarray(off_h[:k + 1], dtype=np.int64)
+    nas = np.ascontiguousarray(na_h[:k], dtype=np.int64)
+    threads = cpu_threads()
+    # contiguous pair ranges of about equal element counts
+    cuts = np.searchsorted(offs, np.linspace(0, elems, threads + 1)).astype(np.int64)
+    cuts[0], cuts[-1] = 0, k
+    ranges = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    oracle.merge_batched(host, offs, nas, pairs=(0, min(k, 8)), out=out)
+    t = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda r: oracle.merge_batched(host, offs, nas, pairs=r, out=out), ranges))
+    dt = time.perf_counter() - t
+    return {"value": round(elems / dt / 1e9, 4), "unit": "Gelem/s", "cores": threads,
+            "kind": "oracle", "host": host_info(),
+            "sample": f"the first {k} pairs of the batch ({elems} elements): the oracle's "
+                      f"batched two-pointer merge, contiguous pair ranges on {threads} host "
+                      f"threads, {dt:.2f} s"}
 
 
 def bench_heavy_ties(args):
@@ -584,11 +704,22 @@ def bench_sort(args):
         passes += 1
     # run formation + every pass read and write 8 bytes per element
     alg = N * 8 * 2 * (passes + 1)
+    # run formation alone (the sort's first phase)
+    rk, rp = torch.empty_like(keys), torch.empty_like(pay)
+
+    def runs_only():
+        sm.sort_runs(keys, run_len, pay, out_keys=rk, out_payloads=rp, stream=stream)
+
+    runs_only()
+    runs_ms = _events_ms(runs_only, 3, stream)
+    del rk, rp
     res = {"workload": f"N=2^28 uint32 keys uniform in [0, 2^24), uint32 payload = index, "
                        f"runs of {run_len}, {passes} merge passes",
            "Gelem/s": round(N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3),
            "passes": passes, "output_sorted": sorted_ok,
-           "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1)}
+           "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1),
+           "run_formation_ms": round(runs_ms, 3),
+           "cpu_baseline": None if args.no_cpu_baseline else sort_cpu_baseline(keys, pay)}
     # the same sort with learned cross ranks in every pass: one model of the
     # keys' distribution, trained on the first 2^20 keys
     from paper_1202_6575_amd import learned
@@ -623,6 +754,23 @@ def bench_sort(args):
                       "probes_per_rank": round(float(c[1]) / max(int(c[0]), 1), 2),
                       "uninformed_probes_per_rank": round(float(z[1]) / max(int(z[0]), 1), 2)}
     return res
+
+
+def sort_cpu_baseline(keys, pay, sample: int = 1 << 22):
+    """The oracle's stable sort (runs of 512 sorted, then pairwise merge
+    rounds, all on one host thread) on the first `sample` (key, index) pairs
+    of the same input."""
+    import oracle
+    k = keys[:sample].cpu().numpy()
+    p = pay[:sample].cpu().numpy()
+    t = time.perf_counter()
+    oracle.sort(k, p, run_len=512)
+    dt = time.perf_counter() - t
+    return {"value": round(sample / dt / 1e9, 4), "unit": "Gelem/s", "cores": 1,
+            "kind": "oracle", "host": host_info(),
+            "sample": f"the first {sample} (key, index) pairs of the 2^28 input, oracle stable "
+                      f"sort (512-runs, then merge rounds), one thread, {dt:.2f} s; a 2^28 sort "
+                      f"takes 28/22 times as many compares per element"}
 
 
 def _bin_label(k: int) -> str:

@@ -234,6 +234,19 @@ SM_API int stable_merge_sort(const void *keys, const uint32_t *payloads, int64_t
                              void *ws, size_t ws_bytes, const sm_options *opt, void *stream);
 
 /*
+ * The merge sort's first phase alone (Section 3: the blocks are sorted
+ * first, then merged): every run keys[k * run, min((k + 1) * run, N)) is
+ * stably sorted on its own into the same range of out_keys, payloads
+ * (optional) travelling with their keys.  run is 256, 512, 1024, 2048 or,
+ * for 32-bit keys, 4096.  out_keys may be keys itself (in place; likewise
+ * the payloads), any other overlap is SM_ERR_ALIAS.  0 <= N <= 2^38.  No
+ * workspace; asynchronous on `stream`.
+ */
+SM_API int stable_merge_sort_runs(const void *keys, const uint32_t *payloads, int64_t N,
+                                  void *out_keys, uint32_t *out_payloads, int dtype, int run,
+                                  void *stream);
+
+/*
  * Segmented stable sort: every segment keys[offsets[s], offsets[s + 1]) is
  * sorted on its own, payloads (optional) travelling with their keys and
  * equal keys keeping their input order, as stable_merge_sort would sort it

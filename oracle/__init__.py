@@ -60,6 +60,8 @@ def _load():
         lib.orc_rank_high.argtypes = [vp, i64, vp, i64, i32]
         lib.orc_merge.restype = None
         lib.orc_merge.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i32]
+        lib.orc_merge_batched.restype = None
+        lib.orc_merge_batched.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, i32]
         lib.orc_merge_scatter.restype = i32
         lib.orc_merge_scatter.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i32]
         lib.orc_block_start.restype = i64
@@ -138,6 +140,29 @@ def merge(A, B, pa=None, pb=None, descending: bool = False):
     _load().orc_merge(_ptr(A), _ptr(pa), len(A), _ptr(B), _ptr(pb), len(B),
                       _ptr(C), _ptr(pc), _code(A, descending))
     return C, pc
+
+
+def merge_batched(keys, offsets, n_a, pay=None, descending: bool = False, pairs=None,
+                  out=None, out_pay=None):
+    """O5: O1 applied to every pair k = keys[offsets[k]:offsets[k+1]] (first
+    n_a[k] elements A, the rest B).  ``pairs`` = (k0, k1) merges only those
+    pairs into the given ``out`` / ``out_pay`` (the C routine runs without
+    Python's lock, so threads may fill disjoint pair ranges).  Returns
+    (out, out_pay)."""
+    keys = _c(keys)
+    offsets = _c(offsets, np.int64)
+    n_a = _c(n_a, np.int64)
+    has_p = pay is not None
+    pay = _c(pay, np.uint32)
+    if out is None:
+        out = np.empty_like(keys)
+    if has_p and out_pay is None:
+        out_pay = np.empty(len(keys), dtype=np.uint32)
+    k0, k1 = pairs if pairs is not None else (0, len(n_a))
+    _load().orc_merge_batched(_ptr(keys), _ptr(pay), _ptr(offsets), _ptr(n_a), k0, k1,
+                              _ptr(out), _ptr(out_pay) if has_p else None,
+                              _code(keys, descending))
+    return out, out_pay
 
 
 def merge_scatter(A, B, pa=None, pb=None):

@@ -164,6 +164,27 @@ void orc_merge(const void *A, const uint32_t *pa, int64_t n,
     }
 }
 
+/*
+ * O5: many independent merges (Section 3, the merge applied to many pairs).
+ * Pair k occupies keys[offsets[k], offsets[k+1]) with its first n_a[k]
+ * elements as A and the rest as B; its merge lands in the same range of
+ * out.  Pairs [k0, k1) only, so that callers can split a batch.
+ */
+void orc_merge_batched(const void *keys, const uint32_t *pay, const int64_t *offsets,
+                       const int64_t *n_a, int64_t k0, int64_t k1,
+                       void *out, uint32_t *out_pay, int dtype)
+{
+    size_t s = key_size(dtype);
+    int64_t k;
+    for (k = k0; k < k1; k++) {
+        int64_t o = offsets[k], n = n_a[k], m = offsets[k + 1] - o - n_a[k];
+        const char *A = (const char *)keys + (size_t)o * s;
+        const char *B = A + (size_t)n * s;
+        orc_merge(A, pay ? pay + o : NULL, n, B, pay ? pay + o + n : NULL, m,
+                  (char *)out + (size_t)o * s, out_pay ? out_pay + o : NULL, dtype);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* O2: closed-form output positions (Section 2, the paragraph after    */
 /* Observation 1: A[i] lands at i + rank_low(A[i], B), B[j] at         */

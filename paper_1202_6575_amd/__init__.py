@@ -22,8 +22,8 @@ import os
 
 import torch
 
-__all__ = ["merge", "merge_noalloc", "partition", "merge_pieces", "merge_batched", "sort", "segmented_sort",
-           "workspace_bytes", "pieces_workspace_bytes", "batched_workspace_bytes",
+__all__ = ["merge", "merge_noalloc", "partition", "merge_pieces", "merge_batched", "sort",
+           "sort_runs", "segmented_sort", "workspace_bytes", "pieces_workspace_bytes", "batched_workspace_bytes",
            "sort_workspace_bytes", "segmented_sort_workspace_bytes", "SMError", "LIB_PATH",
            "DTYPES"]
 
@@ -82,6 +82,8 @@ _lib.stable_merge_batched_workspace_bytes.argtypes = [_i64, _i64, _i32, _i32,
 _lib.stable_merge_sort.restype = _i32
 _lib.stable_merge_sort.argtypes = [_vp, _vp, _i64, _vp, _vp, _i32, _vp, _sz,
                                    ctypes.POINTER(Options), _vp]
+_lib.stable_merge_sort_runs.restype = _i32
+_lib.stable_merge_sort_runs.argtypes = [_vp, _vp, _i64, _vp, _vp, _i32, _i32, _vp]
 _lib.stable_merge_sort_workspace_bytes.restype = _sz
 _lib.stable_merge_sort_workspace_bytes.argtypes = [_i64, _i32, _i32, ctypes.POINTER(Options)]
 _lib.stable_merge_segmented_sort.restype = _i32
@@ -306,6 +308,23 @@ def sort(keys: torch.Tensor, payloads: torch.Tensor | None = None, *,
     _check(_lib.stable_merge_sort(_ptr(keys), _ptr(payloads), N, _ptr(out_keys),
                                   _ptr(out_payloads), code, _ptr(workspace), workspace.numel(),
                                   ctypes.byref(o), _stream_ptr(stream)))
+    return out_keys, out_payloads
+
+
+def sort_runs(keys: torch.Tensor, run: int = 512, payloads: torch.Tensor | None = None, *,
+              out_keys: torch.Tensor | None = None, out_payloads: torch.Tensor | None = None,
+              stream=None):
+    """The merge sort's run formation alone: every run of `run` consecutive
+    elements stably sorted on its own.  Returns (out_keys, out_payloads)."""
+    _require_device(keys, payloads, out_keys, out_payloads)
+    N = keys.numel()
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if payloads is not None and out_payloads is None:
+        out_payloads = torch.empty(N, dtype=torch.uint32, device=keys.device)
+    _check(_lib.stable_merge_sort_runs(_ptr(keys), _ptr(payloads), N, _ptr(out_keys),
+                                       _ptr(out_payloads), _dtype_code(keys), int(run),
+                                       _stream_ptr(stream)))
     return out_keys, out_payloads
 
 

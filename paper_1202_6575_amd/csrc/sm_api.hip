@@ -498,9 +498,8 @@ size_t stable_merge_sort_workspace_bytes(int64_t N, int dtype, int has_payload,
 namespace {
 
 // Argument checks shared by the two sorts (after sort_plan).
-int check_sort_buffers(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
-                       uint32_t* out_payloads, int dtype, const void* ws, size_t ws_bytes,
-                       size_t need) {
+int check_sort_arrays(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                      uint32_t* out_payloads, int dtype) {
     const bool pay = payloads != nullptr;
     if ((payloads == nullptr) != (out_payloads == nullptr))
         return fail(SM_ERR_ARG, "payloads and out_payloads must both be NULL or both non-NULL");
@@ -515,7 +514,17 @@ int check_sort_buffers(const void* keys, const uint32_t* payloads, int64_t N, vo
                  overlap(out_payloads, pb, keys, kb) || overlap(out_keys, kb, payloads, pb) ||
                  overlap(out_keys, kb, out_payloads, pb))))
         return fail(SM_ERR_ALIAS, "outputs overlap inputs other than in place");
-    int rc = check_ws(ws, ws_bytes, need);
+    return SM_OK;
+}
+
+int check_sort_buffers(const void* keys, const uint32_t* payloads, int64_t N, void* out_keys,
+                       uint32_t* out_payloads, int dtype, const void* ws, size_t ws_bytes,
+                       size_t need) {
+    const bool pay = payloads != nullptr;
+    const size_t kb = (size_t)N * key_bytes(dtype), pb = (size_t)N * 4;
+    int rc = check_sort_arrays(keys, payloads, N, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    rc = check_ws(ws, ws_bytes, need);
     if (rc != SM_OK) return rc;
     const char* w = static_cast<const char*>(ws);
     if (overlap(w, need, keys, kb) || overlap(w, need, out_keys, kb) ||
@@ -556,6 +565,22 @@ int stable_merge_sort(const void* keys, const uint32_t* payloads, int64_t N, voi
                       const sm_options* opt, void* stream) {
     return sort_impl(keys, payloads, N, out_keys, out_payloads, dtype, ws, ws_bytes, opt, stream,
                      nullptr);
+}
+
+int stable_merge_sort_runs(const void* keys, const uint32_t* payloads, int64_t N,
+                           void* out_keys, uint32_t* out_payloads, int dtype, int run,
+                           void* stream) {
+    if (!dtype_ok(dtype)) return fail(SM_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (N < 0 || N > (1ll << 38)) return fail(SM_ERR_ARG, "N must be in [0, 2^38]");
+    if (!sm::sort_run_ok(run, dtype))
+        return fail(SM_ERR_ARG, "run must be 256, 512, 1024, 2048 or (32-bit keys) 4096");
+    if (N == 0) return SM_OK;
+    int rc = check_sort_arrays(keys, payloads, N, out_keys, out_payloads, dtype);
+    if (rc != SM_OK) return rc;
+    hipError_t e = sm::launch_sort_runs(dtype, keys, payloads, N, out_keys, out_payloads, run,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "run formation launch");
+    return SM_OK;
 }
 
 int stable_merge_sort_learned(const void* keys, const uint32_t* payloads, int64_t N,

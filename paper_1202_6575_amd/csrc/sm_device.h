@@ -216,6 +216,7 @@ struct PieceDesc {
     int64_t ka0, kb0, out0;
     uint32_t a_f, b_f;
 };
+static_assert(sizeof(PieceDesc) == 32, "descriptors are read as two 16-byte chunks");
 constexpr uint32_t kSuccBit = 0x80000000u;
 __host__ __device__ inline int desc_a(const PieceDesc& d) { return (int)(d.a_f & ~kSuccBit); }
 __host__ __device__ inline int desc_b(const PieceDesc& d) { return (int)(d.b_f & ~kSuccBit); }
@@ -497,6 +498,49 @@ __device__ __forceinline__ void prefetch_whole(const SegPlan& p, __amdgpu_buffer
     if (PAY)
         load_windows_whole<L, R>(rpay, (p.ka_al + p.offA - p.offPA) * 4, p.ncpa,
                                  (p.kb_al + p.offB - p.offPB) * 4, p.ncpb, rp);
+}
+
+// Window loads for keys of arrays of 4 GiB or more (no payloads): each
+// window gets a buffer resource of its own, A's chunks fill the register
+// slots [0, sA) with sA = ceil(nca / L) and B's chunks the slots from sA
+// on, so each slot's load uses one (workgroup-uniform) resource and no slot
+// needs a select between two loads.  RS slots hold any subproblem whose
+// chunks fit RS - 1 full slots.
+template <typename K, int L, int RS>
+__device__ __forceinline__ void prefetch_split(const SegPlan& p, const K* keys, uint64_t nkeys,
+                                               u32x4 (&rk)[RS]) {
+    const int t = threadIdx.x;
+    const char* base = reinterpret_cast<const char*>(keys);
+    const uint64_t bytes = nkeys * sizeof(K);
+    const uint64_t wa0 = (uint64_t)p.ka_al * sizeof(K), wb0 = (uint64_t)p.kb_al * sizeof(K);
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(base + wa0, wa0 < bytes ? bytes - wa0 : 0);
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(base + wb0, wb0 < bytes ? bytes - wb0 : 0);
+    const int sA = (p.nca + L - 1) / L;
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+        const bool isA = i < sA;
+        const int q = (isA ? i : i - sA) * L + t;
+        const int nq = isA ? p.nca : p.ncb;
+        rk[i] = buf_load16(isA ? rA : rB, q < nq ? (uint32_t)q * 16u : kOffNone);
+    }
+}
+
+// Registers -> LDS for prefetch_split's slot layout; the successor slots
+// are patched by the lanes that wrote their chunks.
+template <typename K, int L, int RS>
+__device__ __forceinline__ void commit_split(const SegPlan& p, const u32x4 (&rk)[RS], K* sKey) {
+    constexpr int V = Vec<K>::N;
+    const int t = threadIdx.x;
+    const int sA = (p.nca + L - 1) / L;
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+        const bool isA = i < sA;
+        const int q = (isA ? i : i - sA) * L + t;
+        if (q < (isA ? p.nca : p.ncb))
+            *reinterpret_cast<u32x4*>(sKey + (isA ? q * V : p.wa + q * V)) = rk[i];
+    }
+    if (!p.succA && t == p.qsA % L) sKey[p.offA + p.a] = KeyMax<K>::v;
+    if (!p.succB && t == (p.qsB - p.nca) % L) sKey[p.wa + p.offB + p.b] = KeyMax<K>::v;
 }
 
 // A successor slot whose segment ends its source array must hold the key
@@ -831,7 +875,10 @@ __device__ __forceinline__ void write_out(const E* sArr, int off, int s, E* base
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int q = q0 + r * L + t;
-            if (q < q1) *reinterpret_cast<u32x4*>(base_out + q * V) = v[r];
+            // the merged stream is written once and not read back soon:
+            // non-temporal stores keep it from evicting the cached lines
+            // that the cross-rank searches reuse
+            if (q < q1) __builtin_nontemporal_store(v[r], reinterpret_cast<u32x4*>(base_out + q * V));
         }
     } else {
         for (int q = q0 + t; q < q1; q += L) chunk(q);

@@ -130,11 +130,15 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
 // subproblem w, the loads of w + G and w + 2G (its next two) are in flight
 // in two register sets, so every load has two merges' time to land.  Per
 // step: wait for the oldest set, commit it to LDS, write back w - G, issue
-// the loads of w + 2G into the freed set, merge w.  The write-back precedes the loads, so at the
-// next wait the operations younger than the awaited loads are one
-// write-back and then the other set's loads: waiting until no more than that
-// set's load count is in flight leaves at most that set in flight.
-template <typename K, bool PAY, int L, int R>
+// the loads of w + 2G into the freed set, merge w.  The write-back (and a
+// descriptor load) precede the loads, so at the next wait the operations
+// younger than the awaited loads are one write-back, one descriptor load
+// and then the other set's loads: waiting until no more than that set's
+// load count is in flight leaves at most that set in flight.
+// WHOLE: the arrays are below 4 GiB and one buffer resource spans each;
+// otherwise (keys only) every window gets a resource of its own and the
+// register sets one more slot (prefetch_split).
+template <typename K, bool PAY, int L, int R, bool WHOLE>
 __device__ __forceinline__ void merge_pipelined(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
@@ -149,6 +153,30 @@ __device__ __forceinline__ void merge_pipelined(
     const int64_t w0 = blockIdx.x;
     const int64_t w1 = P;
     if (w0 >= w1) return;
+    // Descriptors are read one step before their plan is needed, with vector
+    // loads (a scalar load would be waited for at the next LDS wait, which
+    // covers scalar loads too): the loads of step w's next-but-two
+    // descriptor go out with its prefetch and are complete at the next
+    // step's wait.  Past the range a load returns zeros: an empty plan.
+    const __amdgpu_buffer_rsrc_t rdesc = make_rsrc(desc, (uint64_t)w1 * sizeof(PieceDesc));
+    auto desc_load = [&](int64_t w, u32x4& lo, u32x4& hi) {
+        const uint32_t o = w < w1 ? (uint32_t)(w * (int64_t)sizeof(PieceDesc)) : kOffNone;
+        lo = buf_load16(rdesc, o);
+        hi = buf_load16(rdesc, o + 16u);
+    };
+    auto desc_from = [&](const u32x4& lo, const u32x4& hi) {
+        PieceDesc d;
+        const uint32_t w0_ = __builtin_amdgcn_readfirstlane(lo.x), w1_ = __builtin_amdgcn_readfirstlane(lo.y);
+        const uint32_t w2_ = __builtin_amdgcn_readfirstlane(lo.z), w3_ = __builtin_amdgcn_readfirstlane(lo.w);
+        const uint32_t w4_ = __builtin_amdgcn_readfirstlane(hi.x), w5_ = __builtin_amdgcn_readfirstlane(hi.y);
+        d.ka0 = (int64_t)(((uint64_t)w1_ << 32) | w0_);
+        d.kb0 = (int64_t)(((uint64_t)w3_ << 32) | w2_);
+        d.out0 = (int64_t)(((uint64_t)w5_ << 32) | w4_);
+        d.a_f = __builtin_amdgcn_readfirstlane(hi.z);
+        d.b_f = __builtin_amdgcn_readfirstlane(hi.w);
+        if (!desc_ok(d, nkeys, nout, cap)) d.a_f = d.b_f = 0;
+        return make_plan<K, PAY>(d);
+    };
     auto plan_of = [&](int64_t w) {
         PieceDesc d;
         d.ka0 = d.kb0 = d.out0 = 0;
@@ -159,31 +187,44 @@ __device__ __forceinline__ void merge_pipelined(
         }
         return make_plan<K, PAY>(d);
     };
-    u32x4 rkA[R], rpA[R], rkB[R], rpB[R];
+    static_assert(WHOLE || !PAY, "arrays of 4 GiB or more: keys-only form");
+    constexpr int RS = WHOLE ? R : R + 1;   // key register slots per set
+    u32x4 rkA[RS], rpA[R], rkB[RS], rpB[R];
     SegPlan cur = plan_of(w0);
     SegPlan nxt = plan_of(w0 + G);
+    u32x4 dlo, dhi;
+    desc_load(w0 + 2 * G, dlo, dhi);
+    // the descriptor loads must stay older than both sets' loads (the waits
+    // below count on it): no instruction moves across this point
+    __builtin_amdgcn_sched_barrier(0);
     SegPlan prev = cur;
     // Every step issues its loads, also for a subproblem past the range (an
     // empty one, whose few loads are never used): the awaited set is then
     // always older than the other set's loads on every path, which is what
     // lets the wait below (and the compiler's own) leave that set in flight.
-    // the launcher uses this kernel only for arrays below 4 GiB: one buffer
-    // resource spans each whole array
     const __amdgpu_buffer_rsrc_t rkeys = make_rsrc(keys, (uint64_t)nkeys * sizeof(K));
     const __amdgpu_buffer_rsrc_t rpay = make_rsrc(PAY ? pay : nullptr, PAY ? (uint64_t)nkeys * 4 : 0);
-    prefetch_whole<K, PAY, L, R>(cur, rkeys, rpay, rkA, rpA);
-    prefetch_whole<K, PAY, L, R>(nxt, rkeys, rpay, rkB, rpB);
-    auto step = [&](u32x4 (&rk)[R], u32x4 (&rp)[R], int64_t w) {
-        const SegPlan nn = plan_of(w + 2 * G);
+    auto load = [&](const SegPlan& p, u32x4 (&rk)[RS], u32x4 (&rp)[R]) {
+        if constexpr (WHOLE) prefetch_whole<K, PAY, L, R>(p, rkeys, rpay, rk, rp);
+        else prefetch_split<K, L, RS>(p, keys, (uint64_t)nkeys, rk);
+    };
+    load(cur, rkA, rpA);
+    load(nxt, rkB, rpB);
+    auto step = [&](u32x4 (&rk)[RS], u32x4 (&rp)[R], int64_t w) {
         // the staging and memory phase runs at raised priority, so that the
         // waves of a SIMD commit, pass the barrier and issue their stores
         // and loads before the others' merges
         __builtin_amdgcn_s_setprio(2);
-        wait_vm<PAY ? 2 * R : R>();
-        commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
+        wait_vm<PAY ? 2 * R : RS>();
+        if constexpr (WHOLE) commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
+        else commit_split<K, L, RS>(cur, rk, sp.sKey);
         __syncthreads();
         if (w > w0) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
-        prefetch_whole<K, PAY, L, R>(nn, rkeys, rpay, rk, rp);
+        // the descriptor loaded a step ago has landed (the wait above)
+        const SegPlan nn = desc_from(dlo, dhi);
+        desc_load(w + 3 * G, dlo, dhi);
+        __builtin_amdgcn_sched_barrier(0);
+        load(nn, rk, rp);
         __builtin_amdgcn_s_setprio(0);
         if (cur.s > 0)
             merge_lanes<K, PAY, L, (!PAY || R <= 3)>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx,
@@ -206,20 +247,20 @@ __device__ __forceinline__ void merge_pipelined(
 // Four waves per SIMD need at most 128 registers per lane: four workgroups
 // per compute unit then fit both registers and LDS.  64-bit keys with
 // payloads need more (the wide form, three workgroups).
-template <typename K, bool PAY, int L, int R>
+template <typename K, bool PAY, int L, int R, bool WHOLE>
 __global__ __launch_bounds__(L) __attribute__((amdgpu_waves_per_eu(4))) void merge_pipelined_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
     const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
-    merge_pipelined<K, PAY, L, R>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
+    merge_pipelined<K, PAY, L, R, WHOLE>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
 }
 
-template <typename K, bool PAY, int L, int R>
+template <typename K, bool PAY, int L, int R, bool WHOLE>
 __global__ __launch_bounds__(L) void merge_pipelined_wide_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
     const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
-    merge_pipelined<K, PAY, L, R>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
+    merge_pipelined<K, PAY, L, R, WHOLE>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
 }
 
 // One workgroup per subproblem, staged straight into LDS; for subproblems
@@ -542,28 +583,32 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
                                     uint32_t* out_pay, int64_t nout, const PieceDesc* desc,
                                     int64_t P, const int64_t* P_dev, uint32_t cap, hipStream_t st) {
     constexpr int L = kMergeThreads;
-    // two register sets in flight where they fit the register budget and one
-    // buffer resource spans each array
-    const bool whole = (uint64_t)nkeys * sizeof(K) < (1ull << 32) - 4096;
+    // two register sets in flight where they fit the register budget; one
+    // buffer resource spans each array below 4 GiB, larger arrays take one
+    // per window
+    const bool whole = (uint64_t)nkeys * sizeof(K) < (1ull << 32) - 4096 &&
+                       (uint64_t)nout * sizeof(K) < (1ull << 32) - 4096;
     if constexpr (R <= 5) {
-        if (whole) {
-            auto go = [&](auto kern, std::atomic<bool>& attr2,
-                          std::atomic<uint64_t>& occ) -> hipError_t {
-                const hipError_t e = allow_big_lds_once(kern, attr2);
-                if (e != hipSuccess) return e;
-                const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
-                int64_t grid = (int64_t)device_cu_count() * resident_per_cu(kern, lds, occ);
-                if (grid > P) grid = P;
-                kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P,
-                                                     P_dev, cap);
-                return hipGetLastError();
-            };
-            static std::atomic<bool> attr2{false};
-            static std::atomic<uint64_t> occ2{0};
-            if constexpr (sizeof(K) == 8 && PAY)
-                return go(merge_pipelined_wide_kernel<K, PAY, L, R>, attr2, occ2);
-            else
-                return go(merge_pipelined_kernel<K, PAY, L, R>, attr2, occ2);
+        auto go = [&](auto kern, std::atomic<bool>& attr2,
+                      std::atomic<uint64_t>& occ) -> hipError_t {
+            const hipError_t e = allow_big_lds_once(kern, attr2);
+            if (e != hipSuccess) return e;
+            const uint32_t lds = MergeSmem<K, PAY, L>::bytes(cap);
+            int64_t grid = (int64_t)device_cu_count() * resident_per_cu(kern, lds, occ);
+            if (grid > P) grid = P;
+            kern<<<(unsigned)grid, L, lds, st>>>(keys, pay, nkeys, out, out_pay, nout, desc, P,
+                                                 P_dev, cap);
+            return hipGetLastError();
+        };
+        static std::atomic<bool> attr2{false}, attr3{false};
+        static std::atomic<uint64_t> occ2{0}, occ3{0};
+        if constexpr (sizeof(K) == 8 && PAY) {
+            if (whole) return go(merge_pipelined_wide_kernel<K, PAY, L, R, true>, attr2, occ2);
+        } else if constexpr (PAY) {
+            if (whole) return go(merge_pipelined_kernel<K, PAY, L, R, true>, attr2, occ2);
+        } else {
+            return whole ? go(merge_pipelined_kernel<K, PAY, L, R, true>, attr2, occ2)
+                         : go(merge_pipelined_kernel<K, PAY, L, R, false>, attr3, occ3);
         }
     }
     auto kern = merge_persistent_kernel<K, PAY, L, R>;

@@ -40,6 +40,11 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
                        hipStream_t st, const int64_t* seg_offsets = nullptr,
                        int64_t seg_count = 0, const LearnedSearch* ls = nullptr);
 
+// Run formation alone: every run of `run` consecutive elements stably
+// sorted into out (out may be keys itself).
+hipError_t launch_sort_runs(int dtype, const void* keys, const uint32_t* pay, int64_t N,
+                            void* out_keys, uint32_t* out_pay, int run, hipStream_t st);
+
 // Sets *bad (device int, cleared beforehand) unless the offsets run from 0
 // to N without decreasing and no segment is longer than max_len.
 hipError_t launch_seg_check(const int64_t* offsets, int64_t count, int64_t N, int64_t max_len,

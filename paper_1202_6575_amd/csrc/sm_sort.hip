@@ -301,6 +301,19 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
     return hipSuccess;
 }
 
+hipError_t launch_sort_runs(int dtype, const void* keys, const uint32_t* pay, int64_t N,
+                            void* out_keys, uint32_t* out_pay, int run, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    with_key_type(dtype, [&](auto z) {
+        using K = decltype(z);
+        e = pay ? launch_runs_t<K, true>(static_cast<const K*>(keys), pay, N,
+                                         static_cast<K*>(out_keys), out_pay, run, nullptr, 0, st)
+                : launch_runs_t<K, false>(static_cast<const K*>(keys), nullptr, N,
+                                          static_cast<K*>(out_keys), nullptr, run, nullptr, 0, st);
+    });
+    return e;
+}
+
 hipError_t launch_seg_check(const int64_t* offsets, int64_t count, int64_t N, int64_t max_len,
                             int* bad, hipStream_t st) {
     if (count <= 0) return hipSuccess;

@@ -317,3 +317,17 @@ def test_noalloc_error_paths(sm):
     hdr = open(os.path.join(HEADER_DIR, "stablemerge.h")).read()
     mt = re.search(r"#define SM_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
     assert mt and sm.NOALLOC_SCRATCH_BYTES == int(mt.group(1)) << int(mt.group(2))
+
+
+def test_sort_runs_error_paths(sm):
+    """stable_merge_sort_runs checks its arguments before any launch."""
+    def call(keys=0x10000, pay=None, N=1000, out=0x20000, opay=None, dtype=1, run=512):
+        return sm._lib.stable_merge_sort_runs(keys, pay, N, out, opay, dtype, run, None)
+    assert call(dtype=6) == -2
+    assert call(N=-1) == -1
+    assert call(run=300) == -1
+    assert call(run=4096, dtype=2) == -1          # 4096 only for 32-bit keys
+    assert call(pay=0x40000) == -1
+    assert call(keys=0x10008) == -1
+    assert call(out=0x10000 + 16) == -3           # partial overlap
+    assert call(N=0) == 0

@@ -26,19 +26,6 @@ def make_batch(g, lengths, alpha, dtype, gap=0):
     return np.concatenate(parts), np.array(offsets, np.int64), np.array(n_a, np.int64)
 
 
-def oracle_batched(keys, offsets, n_a, pay):
-    """Each pair merged by the oracle; ranges outside every pair are None."""
-    out_k, out_p = [], []
-    for k in range(len(n_a)):
-        lo, hi, na = offsets[k], offsets[k + 1], n_a[k]
-        rk, rp = oracle.merge(keys[lo:lo + na], keys[lo + na:hi],
-                              None if pay is None else pay[lo:lo + na],
-                              None if pay is None else pay[lo + na:hi])
-        out_k.append(rk)
-        out_p.append(rp)
-    return out_k, out_p
-
-
 def check_batched(keys, offsets, n_a, with_pay=True, **kw):
     pay = np.arange(len(keys), dtype=np.uint32) if with_pay else None
     ck, cp = sm.merge_batched(dev(keys), dev(offsets), dev(n_a),
@@ -46,12 +33,12 @@ def check_batched(keys, offsets, n_a, with_pay=True, **kw):
     torch.cuda.synchronize()
     ck = host(ck)
     cp = None if cp is None else host(cp)
-    rk, rp = oracle_batched(keys, offsets, n_a, pay)
+    rk, rp = oracle.merge_batched(keys, offsets, n_a, pay)
     for k in range(len(n_a)):
         lo, hi = offsets[k], offsets[k + 1]
-        assert np.array_equal(ck[lo:hi], rk[k]), f"pair {k} keys differ"
+        assert np.array_equal(ck[lo:hi], rk[lo:hi]), f"pair {k} keys differ"
         if with_pay:
-            assert np.array_equal(cp[lo:hi], rp[k]), f"pair {k} payloads differ"
+            assert np.array_equal(cp[lo:hi], rp[lo:hi]), f"pair {k} payloads differ"
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -120,9 +107,9 @@ def test_batched_invalid_pair_skipped():
     sm.merge_batched(dev(keys), dev(offsets), dev(bad), out_keys=out)
     torch.cuda.synchronize()
     got = host(out)
-    rk, _ = oracle_batched(keys, offsets, n_a, None)
-    assert np.array_equal(got[offsets[0]:offsets[1]], rk[0])
-    assert np.array_equal(got[offsets[2]:offsets[3]], rk[2])
+    rk, _ = oracle.merge_batched(keys, offsets, n_a)
+    assert np.array_equal(got[offsets[0]:offsets[1]], rk[offsets[0]:offsets[1]])
+    assert np.array_equal(got[offsets[2]:offsets[3]], rk[offsets[2]:offsets[3]])
     assert (got[offsets[1]:offsets[2]] == -1).all()
 
 
@@ -176,3 +163,19 @@ def test_batched_65536_pairs_to_2e20_sampled():
         inp = host(keys[lo:hi])
         rk, _ = oracle.merge(inp[:na[k]], inp[na[k]:])
         assert np.array_equal(host(ck[lo:hi]), rk), f"pair {k}"
+    # every pair at full size, on the GPU in groups of pairs: each output
+    # range non-decreasing and holding the same multiset as its input
+    k0 = 0
+    while k0 < count:
+        k1 = int(np.searchsorted(off, off[k0] + (1 << 28), side="right")) - 1
+        k1 = max(k0 + 1, min(k1, count))
+        lo, hi = int(off[k0]), int(off[k1])
+        flush(f"literal batch properties pairs [{k0}, {k1})")
+        pid = torch.repeat_interleave(torch.arange(k0, k1, device=keys.device),
+                                      offsets[k0 + 1:k1 + 1] - offsets[k0:k1])
+        comp_in = (pid << 21) | keys[lo:hi].to(torch.int64)
+        comp_out = (pid << 21) | ck[lo:hi].to(torch.int64)
+        assert bool((comp_out[1:] >= comp_out[:-1]).all()), f"pairs [{k0}, {k1}) unsorted"
+        assert torch.equal(torch.sort(comp_in).values, comp_out), f"pairs [{k0}, {k1}) multiset"
+        del pid, comp_in, comp_out
+        k0 = k1

@@ -138,6 +138,54 @@ def test_rank_search_matches_oracle(dtype, is_high):
                     assert (rr, pp, ff) == (r[i], pr[i], bool(fb[i])), i
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("is_high", [False, True])
+def test_rank_search_beyond_2e31(is_high):
+    """An array of 2^31 + 2^20 uint32 keys (the 64-bit bisection of the
+    corrective search): X[i] = floor(i / 2), so rank_low(q) = 2q and
+    rank_high(q) = 2q + 2 for q below the largest key; guesses far off and
+    a window that forces the fallback half the time."""
+    N = (1 << 31) + (1 << 20)
+    X = (torch.arange(N, device="cuda:0", dtype=torch.int64) // 2).to(torch.uint32)
+    g = np.random.default_rng(31)
+    q = np.sort(g.integers(0, N // 2 - 1, size=4096)).astype(np.int64)
+    exact = 2 * q + (2 if is_high else 0)
+    guess = np.clip(exact + g.integers(-(1 << 31), 1 << 31, size=len(q)), 0, N)
+    flush(f"rank search beyond 2^31 high={is_high}")
+    r, _, fb = learned.rank_search(X, dev(q.astype(np.uint32)), dev(guess), is_high, 1, 1 << 30)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(r), exact)
+    assert 0 < int(host(fb).sum()) < len(q)
+    del X
+
+
+@pytest.mark.slow
+def test_merge_learned_lognormal_2e28_full():
+    """The learned-partition workload at full size: n = m = 2^28 uint32 keys
+    from the log-normal mixture, blocks of 16, trained models; the whole
+    output equals the oracle's merge."""
+    import datagen.torch_gen as tg
+    n = m = 1 << 28
+    flush("learned 2^28 generate")
+    A = tg.lognormal_mixture(n, seed=datagen.BASE_SEED + 6)
+    B = tg.lognormal_mixture(m, seed=datagen.BASE_SEED + 7)
+    pb, lb = learned.train_rank_model(B, A, False, 1 << 18, 400, seed=11)
+    pa, la = learned.train_rank_model(A, B, True, 1 << 18, 400, seed=12)
+    torch.cuda.synchronize()
+    s0a = learned.step0_from_loss(float(host(lb)[0]), m)
+    s0b = learned.step0_from_loss(float(host(la)[0]), n)
+    keys = torch.cat([A, B])
+    flush("learned 2^28 merge")
+    ok, _, hist, cnt = learned.merge_learned(keys, n, m, pb, pa, s0a, s0b, 16, 1 << 24)
+    torch.cuda.synchronize()
+    got = host(ok)
+    c = host(cnt).astype(np.int64)
+    assert c[0] == 2 * (n // 16)
+    flush("learned 2^28 oracle")
+    ref, _ = oracle.merge(host(A), host(B))
+    assert np.array_equal(got, ref)
+
+
 def train_pair(A, B, samples=1 << 15, steps=400):
     dA, dB = dev(A), dev(B)
     pb, lb = learned.train_rank_model(dB, dA, False, samples, steps, seed=11)   # B's CDF, A's queries

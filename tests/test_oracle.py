@@ -164,6 +164,34 @@ def test_merge_brute_force(dtype):
         assert np.array_equal(ak, rk) and np.array_equal(ap, rp)
 
 
+@pytest.mark.parametrize("dtype", [np.int32, np.uint64, np.float32])
+def test_merge_batched_brute_force(dtype):
+    """O5 (every pair merged on its own) against the brute-force stable sort
+    of each pair's tagged elements; empty pairs, empty sides and m > n
+    included, and a pair range merged alone leaves the rest untouched."""
+    g = np.random.default_rng(29)
+    lengths = [(0, 0), (5, 0), (0, 7), (1, 1)] + [(int(g.integers(0, 30)), int(g.integers(0, 30)))
+                                                  for _ in range(60)]
+    parts, offsets, n_a = [], [0], []
+    for n, m in lengths:
+        parts += [rand_sorted(g, n, 9, dtype), rand_sorted(g, m, 9, dtype)]
+        offsets.append(offsets[-1] + n + m)
+        n_a.append(n)
+    keys = np.concatenate(parts).astype(dtype)
+    offsets, n_a = np.array(offsets, np.int64), np.array(n_a, np.int64)
+    pay = g.integers(0, 2 ** 32, size=len(keys), dtype=np.uint64).astype(np.uint32)
+    ck, cp = oracle.merge_batched(keys, offsets, n_a, pay)
+    for k, (n, m) in enumerate(lengths):
+        lo = offsets[k]
+        rk, rp = brute_merge(keys[lo:lo + n], keys[lo + n:lo + n + m], pay[lo:lo + n],
+                             pay[lo + n:lo + n + m])
+        assert np.array_equal(ck[lo:lo + n + m], rk) and np.array_equal(cp[lo:lo + n + m], rp)
+    out = np.full(len(keys), 7, dtype=dtype)
+    oracle.merge_batched(keys, offsets, n_a, pairs=(10, 20), out=out)
+    assert np.all(out[:offsets[10]] == 7) and np.all(out[offsets[20]:] == 7)
+    assert np.array_equal(out[offsets[10]:offsets[20]], ck[offsets[10]:offsets[20]])
+
+
 def test_merge_keys_only():
     g = np.random.default_rng(3)
     A, B = rand_sorted(g, 100, 20, np.uint32), rand_sorted(g, 70, 20, np.uint32)
