@@ -133,6 +133,23 @@ def _pmc_per_dispatch(run_dir: str, counter: str):
     return {k: (sum(v) / len(v) if v else None) for k, v in vals.items()}
 
 
+def _pmc_by_kernel(run_dir: str, counter: str):
+    """{kernel name (template arguments kept, parameters dropped): (mean
+    KiB per dispatch, dispatches)} for one counter."""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            v = acc.setdefault(name, [0.0, 0])
+            v[0] += float(r["Counter_Value"])
+            v[1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
 def summarize_trace(trace_dir: str, warmup: int, out_path: str = TRACE_FILE):
     """Per-dispatch durations of the merge kernel from a rocprofv3
     --kernel-trace (csv) of this benchmark: the first `warmup` dispatches
@@ -183,6 +200,20 @@ def summarize_pmc(fetch_dir: str, write_dir: str, log2n: int, out_path: str = PM
            "algorithmic_bytes_per_launch": (n + m) * 2 * 4}
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
+    # every kernel of the run: mean counters per dispatch, scaled alike
+    fa = _pmc_by_kernel(fetch_dir, "FETCH_SIZE")
+    wa = _pmc_by_kernel(write_dir, "WRITE_SIZE")
+    table = {}
+    for name in sorted(set(fa) | set(wa)):
+        fk, fn = fa.get(name, (None, 0))
+        wk, wn = wa.get(name, (None, 0))
+        table[name] = {"dispatches": max(fn, wn),
+                       "fetch_bytes_per_dispatch": None if fk is None else fk * 1024.0 * sf,
+                       "write_bytes_per_dispatch": None if wk is None else wk * 1024.0 * sw}
+    all_path = os.path.join(os.path.dirname(out_path), "library_kernels_pmc.json")
+    with open(all_path, "w") as fh:
+        json.dump({"source_hash": kernel_source_hash(), "fetch_scale": sf, "write_scale": sw,
+                   "kernels": table}, fh, indent=1)
     print(json.dumps(out))
 
 
@@ -198,9 +229,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, sort and learned measurements")
     ap.add_argument("--extras",
-                    default="heavy_ties,skewed,batched,batched_literal,sort,learned,descending",
+                    default="heavy_ties,skewed,batched,batched_literal,sort,sort_learned,"
+                            "learned,descending",
                     help="comma-separated subset of heavy_ties, skewed, batched, "
-                         "batched_literal, sort, learned, descending")
+                         "batched_literal, sort, sort_learned (the sort with one learned "
+                         "model; needs sort), learned, descending")
     ap.add_argument("--sort-run", type=int, default=512, help="run length of the merge sort")
     ap.add_argument("--batch-log2max", type=int, default=15,
                     help="batched pairs: totals log-uniform in [16, 2^this]")
@@ -364,7 +397,7 @@ def main():
             log(f"bench: batched_literal {json.dumps(res['batched_literal'])}")
             torch.cuda.empty_cache()
         if "sort" in extras:
-            res["sort"] = bench_sort(args)
+            res["sort"] = bench_sort(args, "sort_learned" in extras)
             log(f"bench: sort {json.dumps(res['sort'])}")
             torch.cuda.empty_cache()
         if "learned" in extras:
@@ -425,6 +458,7 @@ def bench_batched(args, plain_gelems, log2max):
 
     tile, tune_ms = autotune.tune("batched", run, torch.int32, False, total, valid=valid,
                                   use_cache=False)
+    default_ms = tune_ms.get(2368)
     ws = wss[tile]
     for t in list(wss):
         if t != tile:
@@ -486,7 +520,9 @@ def bench_batched(args, plain_gelems, log2max):
             "eager_ms": round(eager_ms, 4), "graph_launches_per_step": 1,
             "graph_replay_matches_eager": graph_ok,
             "autotune": {"tile": tile, "items_per_lane": 2 * tile // 256,
-                         "ms_by_tile": {str(k): round(v, 4) for k, v in tune_ms.items()}},
+                         "ms_tuned": round(tune_ms[tile], 4),
+                         "ms_default_tile_2368": None if default_ms is None else round(default_ms, 4),
+                         "ms_by_tile": {str(t): round(v, 4) for t, v in tune_ms.items()}},
             "roofline": {"bound": "hbm", "achieved": round(alg / (graph_ms * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(alg / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
@@ -672,7 +708,7 @@ def bench_descending(args):
     return res
 
 
-def bench_sort(args):
+def bench_sort(args, with_learned: bool = True):
     """Stable merge sort of 2^28 (uint32 key uniform in [0, 2^24), uint32
     index) pairs: runs of 512 formed in LDS, then 19 merge passes."""
     import numpy as np
@@ -720,6 +756,8 @@ def bench_sort(args):
            "avg_GB/s_over_passes": round(alg / (ms * 1e-3) / 1e9, 1),
            "run_formation_ms": round(runs_ms, 3),
            "cpu_baseline": None if args.no_cpu_baseline else sort_cpu_baseline(keys, pay)}
+    if not with_learned:
+        return res
     # the same sort with learned cross ranks in every pass: one model of the
     # keys' distribution, trained on the first 2^20 keys
     from paper_1202_6575_amd import learned

@@ -154,6 +154,14 @@ def sort_workspace_bytes(N: int, dtype: torch.dtype, has_payload: bool = False, 
                                                       ctypes.byref(o)))
 
 
+def _tuned(op: str, keys: torch.Tensor, has_payload: bool, size: int) -> int:
+    """The block length cached by the autotuner for this call's class, else
+    0 (the library's default)."""
+    from . import autotune
+    got = autotune.lookup(op, keys.dtype, has_payload, size, device=keys.device)
+    return got if got is not None else 0
+
+
 def _require_device(*ts):
     for t in ts:
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
@@ -168,7 +176,9 @@ def merge(keys: torch.Tensor, n: int, m: int | None = None, payloads: torch.Tens
 
     Returns (out_keys, out_payloads); out_payloads is None without payloads.
     Equal keys keep A before B; each source keeps its order.  With
-    descending=True both inputs and the output run from largest to smallest."""
+    descending=True both inputs and the output run from largest to smallest.
+    With tile, p_a and p_b all 0 and no workspace given, the autotuner's
+    cached block length for this size class is used, if there is one."""
     if m is None:
         m = keys.numel() - n
     if keys.numel() < n + m:
@@ -179,6 +189,8 @@ def merge(keys: torch.Tensor, n: int, m: int | None = None, payloads: torch.Tens
         out_keys = torch.empty(n + m, dtype=keys.dtype, device=keys.device)
     if payloads is not None and out_payloads is None:
         out_payloads = torch.empty(n + m, dtype=torch.uint32, device=keys.device)
+    if tile == 0 and p_a == 0 and p_b == 0 and workspace is None:
+        tile = _tuned("merge", keys, payloads is not None, n + m)
     o = _opts(p_a, p_b, tile, validate, descending=descending)
     need = int(_lib.stable_merge_workspace_bytes(n, m, code, int(payloads is not None),
                                                  ctypes.byref(o)))
@@ -260,7 +272,9 @@ def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
 
     Pair k is keys[offsets[k]:offsets[k+1]] with its first n_a[k] elements as
     A; its merge lands in the same range of out_keys.  offsets (count + 1) and
-    n_a (count) are device int64 tensors.  Returns (out_keys, out_payloads)."""
+    n_a (count) are device int64 tensors.  Returns (out_keys, out_payloads).
+    With tile 0 and no workspace given, the autotuner's cached block length
+    for this size class is used, if there is one."""
     _require_device(keys, offsets, n_a, payloads, out_keys, out_payloads, workspace)
     if offsets.dtype != torch.int64 or n_a.dtype != torch.int64:
         raise SMError(-1, "offsets and n_a must be int64")
@@ -273,6 +287,8 @@ def merge_batched(keys: torch.Tensor, offsets: torch.Tensor, n_a: torch.Tensor,
         out_keys = torch.empty_like(keys)
     if payloads is not None and out_payloads is None:
         out_payloads = torch.empty(total, dtype=torch.uint32, device=keys.device)
+    if tile == 0 and workspace is None:
+        tile = _tuned("batched", keys, payloads is not None, total)
     o = _opts(0, 0, tile, validate, descending=descending)
     if workspace is None:
         need = int(_lib.stable_merge_batched_workspace_bytes(count, total, code,

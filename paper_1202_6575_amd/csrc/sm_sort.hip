@@ -22,11 +22,9 @@ namespace sm {
 
 namespace {
 
-// threads sorting one run: two elements each, at most 1024 (the rank
-// searches are chains of dependent LDS reads, so the more waves share a CU
-// the better their latency is hidden)
+// Threads sorting one run: eight consecutive elements each.
 template <int RUN>
-constexpr int run_threads() { return RUN / 2 < 1024 ? RUN / 2 : 1024; }
+constexpr int run_threads() { return RUN / 8; }
 
 template <typename K, bool PAY, int RUN>
 struct RunSmem {
@@ -57,22 +55,96 @@ __device__ __forceinline__ bool seg_slot(const int64_t* __restrict__ offsets, in
     return k < (len + W - 1) / W;
 }
 
+// Eight consecutive elements of the run into registers; positions at or
+// past len hold the largest key (and payload 0).  vec: the eight start on a
+// 16-byte boundary in memory.
+template <typename K, bool PAY>
+__device__ __forceinline__ void load8(const K* keys, const uint32_t* pay, int64_t at, int valid,
+                                      bool vec, K (&k)[8], uint32_t (&p)[8]) {
+    if (vec && valid >= 8) {
+        constexpr int V = 16 / sizeof(K);
+#pragma unroll
+        for (int c = 0; c < 8 / V; ++c) {
+            const u32x4 v = *reinterpret_cast<const u32x4*>(keys + at + c * V);
+            __builtin_memcpy(&k[c * V], &v, 16);
+        }
+        if (PAY) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const u32x4 v = *reinterpret_cast<const u32x4*>(pay + at + c * 4);
+                p[4 * c] = v.x; p[4 * c + 1] = v.y; p[4 * c + 2] = v.z; p[4 * c + 3] = v.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            k[e] = e < valid ? keys[at + e] : KeyMax<K>::v;
+            if (PAY) p[e] = e < valid ? pay[at + e] : 0u;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (!PAY) p[e] = 0u;
+}
+
+template <typename K, bool PAY>
+__device__ __forceinline__ void store8(K* out, uint32_t* out_pay, int64_t at, int valid, bool vec,
+                                       const K (&k)[8], const uint32_t (&p)[8]) {
+    if (vec && valid >= 8) {
+        constexpr int V = 16 / sizeof(K);
+#pragma unroll
+        for (int c = 0; c < 8 / V; ++c) {
+            u32x4 v;
+            __builtin_memcpy(&v, &k[c * V], 16);
+            *reinterpret_cast<u32x4*>(out + at + c * V) = v;
+        }
+        if (PAY) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                u32x4 v;
+                v.x = p[4 * c]; v.y = p[4 * c + 1]; v.z = p[4 * c + 2]; v.w = p[4 * c + 3];
+                *reinterpret_cast<u32x4*>(out_pay + at + c * 4) = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (e < valid) {
+                out[at + e] = k[e];
+                if (PAY) out_pay[at + e] = p[e];
+            }
+        }
+    }
+}
+
 // Stable sort of keys[r0, r0 + len) (len <= RUN) into out[r0, r0 + len):
 // r0 = blockIdx.x * RUN without segments; with segments, the block's slot
 // names a run of a segment, which starts at the segment's start.
+//   1. Every thread sorts its eight elements in registers with the
+//      odd-even transposition network: it only swaps neighbours, and only
+//      when the right key is strictly smaller, so equal keys keep their
+//      order.
+//   2. Rounds w = 8, 16, ..., RUN / 2 merge neighbouring sorted pieces of w
+//      elements.  Thread t produces outputs [8t, 8t + 8) of its pair: the
+//      number i of the pair's first 8t outputs (counted from the pair's
+//      start) that come from the left piece is found by binary search (the
+//      left piece's element a is among them iff a <= the right piece's
+//      element on the same diagonal), then eight steps of the stable
+//      two-pointer merge (right only if strictly smaller) from (i, d - i).
+//      Outputs gather in registers and go to the other LDS buffer, the last
+//      round's straight to memory.
 // Positions past len hold the largest key; they start behind every real
-// element and every round keeps them there (a right element ties behind the
-// whole left piece), so the real elements' order is the stable one.
-template <typename K, bool PAY, int RUN>
+// element and every step keeps them there (equal keys keep their order), so
+// the real elements' order is the stable one.
 // keys / out (and pay / out_pay) may be the same array: a workgroup reads
 // its whole run before it writes any of it.
+template <typename K, bool PAY, int RUN>
 __global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(
     const K* keys, const uint32_t* pay, int64_t N, K* out, uint32_t* out_pay,
     const int64_t* __restrict__ seg_offsets, int64_t seg_count) {
     constexpr int T = run_threads<RUN>();
-    constexpr int E = RUN / T;
-    static_assert(RUN % T == 0 && (RUN & (RUN - 1)) == 0, "RUN: power of two, multiple of T");
-    __shared__ RunSmem<K, PAY, RUN> s;
+    static_assert(RUN % 16 == 0 && (RUN & (RUN - 1)) == 0, "RUN: a power of two");
+    __shared__ __align__(16) RunSmem<K, PAY, RUN> s;
     const int t = threadIdx.x;
     int64_t r0 = (int64_t)blockIdx.x * RUN, end = N;
     if (seg_offsets) {
@@ -83,46 +155,72 @@ __global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(
     }
     const int64_t rem = end - r0;
     const int len = rem < RUN ? (int)rem : RUN;
+    const int o0 = 8 * t;
+    const int valid = len - o0;   // may be <= 0
+    // 16-byte access needs the run start (and payload start) aligned
+    const bool vec = ((reinterpret_cast<uintptr_t>(keys + r0) | reinterpret_cast<uintptr_t>(out + r0)) & 15) == 0 &&
+                     (!PAY || ((reinterpret_cast<uintptr_t>(pay + r0) |
+                                reinterpret_cast<uintptr_t>(out_pay + r0)) & 15) == 0);
+    K k[8];
+    uint32_t p[8];
+    load8<K, PAY>(keys, pay, r0 + o0, valid, vec, k, p);
+
+    // 1. odd-even transposition: eight rounds of neighbour swaps
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = t + T * e;
-        s.key[0][i] = i < len ? keys[r0 + i] : KeyMax<K>::v;
-        if (PAY) s.pay[0][i] = i < len ? pay[r0 + i] : 0u;
-    }
-    __syncthreads();
-    int cur = 0;
-    for (int w = 1; w < RUN; w <<= 1) {
-        K kv[E];
-        uint32_t pv[E];
-        int dst[E];
+    for (int r = 0; r < 8; ++r) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = t + T * e;
-            const K x = s.key[cur][i];
-            const int lo = i & ~(2 * w - 1);   // start of the pair of pieces
-            const bool right = (i & w) != 0;
-            const K* other = &s.key[cur][right ? lo : lo + w];
-            const int r = right ? upper_bound_lds<K>(other, w, x) : lower_bound_lds<K>(other, w, x);
-            dst[e] = lo + (i - lo - (right ? w : 0)) + r;
-            kv[e] = x;
-            if (PAY) pv[e] = s.pay[cur][i];
+        for (int e = r & 1; e + 1 < 8; e += 2) {
+            const bool sw = k[e + 1] < k[e];
+            const K lo = sw ? k[e + 1] : k[e], hi = sw ? k[e] : k[e + 1];
+            k[e] = lo;
+            k[e + 1] = hi;
+            if (PAY) {
+                const uint32_t pl = sw ? p[e + 1] : p[e], ph = sw ? p[e] : p[e + 1];
+                p[e] = pl;
+                p[e + 1] = ph;
+            }
         }
+    }
+
+    // 2. merge rounds
+    int cur = 0;
+#pragma unroll 1
+    for (int w = 8; w < RUN; w <<= 1) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            s.key[cur ^ 1][dst[e]] = kv[e];
-            if (PAY) s.pay[cur ^ 1][dst[e]] = pv[e];
+        for (int e = 0; e < 8; ++e) {
+            s.key[cur][o0 + e] = k[e];
+            if (PAY) s.pay[cur][o0 + e] = p[e];
         }
         __syncthreads();
+        const int base = o0 & ~(2 * w - 1);
+        const int d = o0 - base;
+        const K* A = &s.key[cur][base];
+        const K* B = A + w;
+        int lo = d > w ? d - w : 0, hi = d < w ? d : w;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (!(B[d - 1 - mid] < A[mid])) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, j = d - lo;
+        K ka = A[i < w ? i : w - 1], kb = B[j < w ? j : w - 1];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const bool takeB = j < w && (i >= w || kb < ka);
+            k[e] = takeB ? kb : ka;
+            if (PAY) p[e] = takeB ? s.pay[cur][base + w + j] : s.pay[cur][base + i];
+            i += !takeB;
+            j += takeB;
+            const K na = A[i < w ? i : w - 1], nb = B[j < w ? j : w - 1];
+            ka = takeB ? ka : na;
+            kb = takeB ? nb : kb;
+        }
+        // the next round writes the other buffer; the one after writes this
+        // one only after the next round's barrier, which every thread passes
+        // only once it has finished reading here
         cur ^= 1;
     }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = t + T * e;
-        if (i < len) {
-            out[r0 + i] = s.key[cur][i];
-            if (PAY) out_pay[r0 + i] = s.pay[cur][i];
-        }
-    }
+    store8<K, PAY>(out, out_pay, r0 + o0, valid, vec, k, p);
 }
 
 // Jobs of merge pass w: job k merges [2kw, min(2kw + w, N)) with
