@@ -26,6 +26,7 @@ namespace {
 template <int RUN>
 constexpr int run_threads() { return RUN / 8; }
 
+// LDS of one run: two buffers of keys (and payloads).
 template <typename K, bool PAY, int RUN>
 struct RunSmem {
     K key[2][RUN];
@@ -120,10 +121,10 @@ __device__ __forceinline__ void store8(K* out, uint32_t* out_pay, int64_t at, in
 // Stable sort of keys[r0, r0 + len) (len <= RUN) into out[r0, r0 + len):
 // r0 = blockIdx.x * RUN without segments; with segments, the block's slot
 // names a run of a segment, which starts at the segment's start.
-//   1. Every thread sorts its eight elements in registers with the
-//      odd-even transposition network: it only swaps neighbours, and only
-//      when the right key is strictly smaller, so equal keys keep their
-//      order.
+//   1. Every thread places its eight elements by their stable ranks: the
+//      rank of element e is the number of the eight with a smaller key plus
+//      the number before e with an equal key (28 comparisons), and e goes to
+//      slot 8t + rank in LDS.
 //   2. Rounds w = 8, 16, ..., RUN / 2 merge neighbouring sorted pieces of w
 //      elements.  Thread t produces outputs [8t, 8t + 8) of its pair: the
 //      number i of the pair's first 8t outputs (counted from the pair's
@@ -131,6 +132,8 @@ __device__ __forceinline__ void store8(K* out, uint32_t* out_pay, int64_t at, in
 //      left piece's element a is among them iff a <= the right piece's
 //      element on the same diagonal), then eight steps of the stable
 //      two-pointer merge (right only if strictly smaller) from (i, d - i).
+//      A step reads only the next element of the side it took; payloads
+//      are read after the eight steps from the positions recorded.
 //      Outputs gather in registers and go to the other LDS buffer, the last
 //      round's straight to memory.
 // Positions past len hold the largest key; they start behind every real
@@ -165,59 +168,74 @@ __global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(
     uint32_t p[8];
     load8<K, PAY>(keys, pay, r0 + o0, valid, vec, k, p);
 
-    // 1. odd-even transposition: eight rounds of neighbour swaps
+    // 1. stable ranks among the eight (a later element with an equal key
+    //    ranks behind), then each element to its slot
+    int rk[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int e = 0; e < 8; ++e) rk[e] = e;
 #pragma unroll
-        for (int e = r & 1; e + 1 < 8; e += 2) {
-            const bool sw = k[e + 1] < k[e];
-            const K lo = sw ? k[e + 1] : k[e], hi = sw ? k[e] : k[e + 1];
-            k[e] = lo;
-            k[e + 1] = hi;
-            if (PAY) {
-                const uint32_t pl = sw ? p[e + 1] : p[e], ph = sw ? p[e] : p[e + 1];
-                p[e] = pl;
-                p[e + 1] = ph;
-            }
+    for (int e = 1; e < 8; ++e) {
+#pragma unroll
+        for (int f = 0; f < e; ++f) {
+            const int c = k[e] < k[f] ? 1 : 0;   // e passes f
+            rk[e] -= c;
+            rk[f] += c;
         }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        s.key[0][o0 + rk[e]] = k[e];
+        if (PAY) s.pay[0][o0 + rk[e]] = p[e];
     }
 
     // 2. merge rounds
     int cur = 0;
 #pragma unroll 1
     for (int w = 8; w < RUN; w <<= 1) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            s.key[cur][o0 + e] = k[e];
-            if (PAY) s.pay[cur][o0 + e] = p[e];
-        }
         __syncthreads();
         const int base = o0 & ~(2 * w - 1);
         const int d = o0 - base;
         const K* A = &s.key[cur][base];
         const K* B = A + w;
+        const K* Bend = B + w;
         int lo = d > w ? d - w : 0, hi = d < w ? d : w;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (!(B[d - 1 - mid] < A[mid])) lo = mid + 1;
             else hi = mid;
         }
-        int i = lo, j = d - lo;
-        K ka = A[i < w ? i : w - 1], kb = B[j < w ? j : w - 1];
+        // pa, pb: the heads of the two pieces (at B and at Bend: exhausted)
+        const K* pa = A + lo;
+        const K* pb = B + (d - lo);
+        K ka = *(pa < B ? pa : B - 1), kb = *(pb < Bend ? pb : Bend - 1);
+        const K* from[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const bool takeB = j < w && (i >= w || kb < ka);
+            const bool takeB = (pb < Bend) & ((pa >= B) | (kb < ka));
             k[e] = takeB ? kb : ka;
-            if (PAY) p[e] = takeB ? s.pay[cur][base + w + j] : s.pay[cur][base + i];
-            i += !takeB;
-            j += takeB;
-            const K na = A[i < w ? i : w - 1], nb = B[j < w ? j : w - 1];
-            ka = takeB ? ka : na;
-            kb = takeB ? nb : kb;
+            from[e] = takeB ? pb : pa;
+            pa += takeB ? 0 : 1;
+            pb += takeB ? 1 : 0;
+            // the next element of the side taken (past its end: a stale
+            // value that the bounds above never let win)
+            const K* nx = takeB ? pb : pa;
+            const K v = *(nx < Bend ? nx : Bend - 1);
+            ka = takeB ? ka : v;
+            kb = takeB ? v : kb;
         }
-        // the next round writes the other buffer; the one after writes this
-        // one only after the next round's barrier, which every thread passes
-        // only once it has finished reading here
+        if (PAY) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) p[e] = s.pay[cur][from[e] - s.key[cur]];
+        }
+        if (2 * w < RUN) {
+            // the other buffer was last read in the round before this one,
+            // which every thread finished before this round's barrier
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                s.key[cur ^ 1][o0 + e] = k[e];
+                if (PAY) s.pay[cur ^ 1][o0 + e] = p[e];
+            }
+        }
         cur ^= 1;
     }
     store8<K, PAY>(out, out_pay, r0 + o0, valid, vec, k, p);
@@ -378,6 +396,7 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
     });
     if (e != hipSuccess) return e;
     int64_t w = run;
+    const uint32_t cap = merge_cap_for_tile((int32_t)tile);
     for (int pass = 0; pass < L.passes; ++pass, w *= 2) {
         // job slots of this pass: one per pair of runs, or (segments) the
         // slot bound at width 2w
@@ -389,9 +408,16 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
         else
             sort_pass_jobs_kernel<<<(unsigned)g, 256, 0, st>>>(N, w, count, jobs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const BatchLayout BL = batch_layout(count, N, tile);
-        e = launch_batch(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, tile,
-                         ws + L.off_batch, BL, st, ls);
+        if (!seg_offsets && 2 * w <= (int64_t)cap) {
+            // a pair of runs fits one merge workgroup: each job is merged
+            // whole, with no cross ranks to find
+            e = launch_merge_desc(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, nullptr,
+                                  cap, st);
+        } else {
+            const BatchLayout BL = batch_layout(count, N, tile);
+            e = launch_batch(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, tile,
+                             ws + L.off_batch, BL, st, ls);
+        }
         if (e != hipSuccess) return e;
         char* tk = src_k; src_k = dst_k; dst_k = tk;
         uint32_t* tp = src_p; src_p = dst_p; dst_p = tp;
