@@ -37,7 +37,7 @@ hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const in
 hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
                              void* out_keys, uint32_t* out_pay, int64_t nout,
                              const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
-                             hipStream_t st);
+                             hipStream_t st, bool packed = false);
 
 // Steps 3-4 plus the merges for small blocks: one lane per subproblem, no
 // descriptors (subproblems of at most kFineCap elements).

@@ -38,6 +38,14 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ ke
 // processing elements of A blocks (Step 3), p_a..p_a+p_b-1 to B blocks
 // (Step 4).  The output position of every subproblem is a_lo + b_lo (the
 // stable-merge position identity of Section 2).
+//
+// The descriptors are stored in output order.  The subproblem of A block i
+// starts with A[x_i], placed after the B block starts y_j < xbar_i (B[y_j]
+// precedes A[x_i] exactly when y_j < rank_low(A[x_i])) and after the A
+// pieces before it: its place is i + #{j : y_j < xbar_i}.  Likewise the
+// subproblem of B block j has place j + #{i : x_i < ybar_j}.  Blocks that
+// start at the end of their array (more blocks than elements) hold empty
+// subproblems; they take the places after all others, A's first.
 __global__ __launch_bounds__(256) void cases_kernel(int64_t n, int64_t m, int64_t p_a,
                                                     int64_t p_b, const int64_t* __restrict__ xbar,
                                                     const int64_t* __restrict__ ybar,
@@ -47,6 +55,21 @@ __global__ __launch_bounds__(256) void cases_kernel(int64_t n, int64_t m, int64_
     const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
     const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
                                       : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
+    // blocks that hold an element; block starts below x (x <= len)
+    const int64_t ne_a = n > 0 ? BA.of(n - 1) + 1 : 0, ne_b = m > 0 ? BB.of(m - 1) + 1 : 0;
+    auto starts_below = [](const Blocks<int64_t>& Bk, int64_t x) {
+        return x <= 0 ? (int64_t)0 : Bk.of(x - 1) + 1;
+    };
+    int64_t place;
+    if (w < p_a) {
+        place = w < ne_a ? w + starts_below(BB, xbar[w] < m ? xbar[w] : m) : ne_b + w;
+    } else {
+        const int64_t j = w - p_a;
+        place = j < ne_b ? j + starts_below(BA, ybar[j] < n ? ybar[j] : n) : p_a + j;
+    }
+    // out of range only for inputs that are not sorted (the subproblems then
+    // overlap); the merge kernel checks every descriptor it reads
+    if (place < 0 || place >= p_a + p_b) place = w;
     PieceDesc d;
     d.ka0 = pc.a_lo;
     d.kb0 = n + pc.b_lo;
@@ -62,7 +85,7 @@ __global__ __launch_bounds__(256) void cases_kernel(int64_t n, int64_t m, int64_
         d.a_f = (uint32_t)(pc.a_hi - pc.a_lo) | (pc.a_hi < n ? kSuccBit : 0u);
         d.b_f = (uint32_t)(pc.b_hi - pc.b_lo) | (pc.b_hi < m ? kSuccBit : 0u);
     }
-    desc[w] = d;
+    desc[place] = d;
 }
 
 // Persistent merge: workgroup g of G merges subproblems g, g + G, g + 2G, ...
@@ -126,6 +149,184 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
     write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
 }
 
+// Packed steps.  With the descriptors in output order, consecutive
+// subproblems chain: each starts in A, in B and in C where the one before
+// ends.  The union of a run of them is then itself a merge subproblem (a
+// contiguous A range, B range and output range), and the element after each
+// of its ranges is the one after the last member's range, so the sentinel
+// rule holds for it as for its members.  A step of the packed form merges
+// the union of up to kPackMax consecutive subproblems that fits the
+// workgroup's capacity: the subproblems average half the capacity (each has
+// at most one block of A and one of B), so a step moves about twice the
+// data.  The lane-level split is applied to the union.  Descriptors that do
+// not chain (another caller's list) are merged one per step.
+constexpr int kPackMax = 4;
+
+struct PackGroup {
+    PieceDesc d;
+    int64_t next;   // list index after the group
+};
+
+// d[0 .. avail) are the list entries from index k on (avail <= kPackMax).
+__device__ __forceinline__ PackGroup pack_group(const PieceDesc (&d)[kPackMax], int avail,
+                                                int64_t k, int64_t nkeys, int64_t nout,
+                                                uint32_t cap) {
+    PackGroup g;
+    g.d.ka0 = g.d.kb0 = g.d.out0 = 0;
+    g.d.a_f = g.d.b_f = 0;
+    g.next = k;
+    if (avail <= 0) return g;
+    g.next = k + 1;
+    if (!desc_ok(d[0], nkeys, nout, cap)) return g;
+    // the union's ends so far (fixed indices only: a runtime index into d
+    // would move the array to memory)
+    int64_t ea = d[0].ka0 + desc_a(d[0]), eb = d[0].kb0 + desc_b(d[0]);
+    int64_t ec = d[0].out0 + desc_a(d[0]) + desc_b(d[0]);
+    uint32_t sa = d[0].a_f & kSuccBit, sb = d[0].b_f & kSuccBit;
+    int cnt = 1;
+    bool open = true;
+#pragma unroll
+    for (int t = 1; t < kPackMax; ++t) {
+        const PieceDesc& e = d[t];
+        const int64_t ee = e.out0 + desc_a(e) + desc_b(e);
+        const bool ok = open && t < avail && desc_ok(e, nkeys, nout, cap) && e.ka0 == ea &&
+                        e.kb0 == eb && e.out0 == ec && ee - d[0].out0 <= (int64_t)cap;
+        if (ok) {
+            ea = e.ka0 + desc_a(e);
+            eb = e.kb0 + desc_b(e);
+            ec = ee;
+            sa = e.a_f & kSuccBit;
+            sb = e.b_f & kSuccBit;
+            cnt = t + 1;
+        }
+        open = ok;
+    }
+    g.d.ka0 = d[0].ka0;
+    g.d.kb0 = d[0].kb0;
+    g.d.out0 = d[0].out0;
+    g.d.a_f = (uint32_t)(ea - d[0].ka0) | sa;
+    g.d.b_f = (uint32_t)(eb - d[0].kb0) | sb;
+    g.next = k + cnt;
+    return g;
+}
+
+// The two-register-set pipeline of merge_pipelined (below) over packed
+// steps of the workgroup's own stretch of the list.  The descriptors of the
+// step after next are read a step ahead: lanes 0..7 load the kPackMax
+// entries from the step's first index (16 bytes each), and the fields are
+// read out of those lanes.
+template <typename K, bool PAY, int L, int R, bool WHOLE>
+__device__ __forceinline__ void merge_pipelined_packed(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
+    K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
+    const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
+    extern __shared__ __align__(16) char smem[];
+    const SmemPtrs<K, PAY, L> sp(smem, cap);
+    if (P_dev) {
+        const int64_t pd = *P_dev;
+        P = pd < P ? (pd > 0 ? pd : 0) : P;
+    }
+    const int64_t G = gridDim.x;
+    const int64_t lo = P * (int64_t)blockIdx.x / G;
+    const int64_t hi = P * ((int64_t)blockIdx.x + 1) / G;
+    if (lo >= hi) return;
+    static_assert(kPackMax * (int)sizeof(PieceDesc) == 8 * 16, "eight lanes load the entries");
+    const __amdgpu_buffer_rsrc_t rdesc = make_rsrc(desc, (uint64_t)hi * sizeof(PieceDesc));
+    const int lane = threadIdx.x & 63;
+    // entries [k, min(k + kPackMax, hi)): lane l < 8 holds bytes [16 l, 16 l + 16)
+    auto desc_load = [&](int64_t k, u32x4& v) {
+        const bool in = lane < 8 && k < hi;
+        v = buf_load16(rdesc, in ? (uint32_t)(k * (int64_t)sizeof(PieceDesc)) + 16u * (uint32_t)lane
+                                 : kOffNone);
+    };
+    auto group_from = [&](const u32x4& v, int64_t k) {
+        PieceDesc d[kPackMax];
+#pragma unroll
+        for (int t = 0; t < kPackMax; ++t) {
+            const uint32_t a0 = __builtin_amdgcn_readlane(v.x, 2 * t), a1 = __builtin_amdgcn_readlane(v.y, 2 * t);
+            const uint32_t b0 = __builtin_amdgcn_readlane(v.z, 2 * t), b1 = __builtin_amdgcn_readlane(v.w, 2 * t);
+            const uint32_t c0 = __builtin_amdgcn_readlane(v.x, 2 * t + 1), c1 = __builtin_amdgcn_readlane(v.y, 2 * t + 1);
+            d[t].ka0 = (int64_t)(((uint64_t)a1 << 32) | a0);
+            d[t].kb0 = (int64_t)(((uint64_t)b1 << 32) | b0);
+            d[t].out0 = (int64_t)(((uint64_t)c1 << 32) | c0);
+            d[t].a_f = __builtin_amdgcn_readlane(v.z, 2 * t + 1);
+            d[t].b_f = __builtin_amdgcn_readlane(v.w, 2 * t + 1);
+        }
+        const int64_t left = hi - k;
+        return pack_group(d, (int)(left < kPackMax ? (left > 0 ? left : 0) : kPackMax), k, nkeys,
+                          nout, cap);
+    };
+    auto group_at = [&](int64_t k) {
+        PieceDesc d[kPackMax];
+#pragma unroll
+        for (int t = 0; t < kPackMax; ++t) {
+            if (k + t < hi) {
+                d[t] = desc[k + t];
+            } else {
+                d[t].ka0 = d[t].kb0 = d[t].out0 = 0;
+                d[t].a_f = d[t].b_f = 0;
+            }
+        }
+        const int64_t left = hi - k;
+        return pack_group(d, (int)(left < kPackMax ? (left > 0 ? left : 0) : kPackMax), k, nkeys,
+                          nout, cap);
+    };
+    static_assert(WHOLE || !PAY, "arrays of 4 GiB or more: keys-only form");
+    constexpr int RS = WHOLE ? R : R + 1;   // key register slots per set
+    u32x4 rkA[RS], rpA[R], rkB[RS], rpB[R];
+    const PackGroup g0 = group_at(lo);
+    const PackGroup g1 = group_at(g0.next);
+    SegPlan cur = make_plan<K, PAY>(g0.d);
+    SegPlan nxt = make_plan<K, PAY>(g1.d);
+    int64_t kcur = lo, knxt = g0.next, knn = g1.next;
+    u32x4 dv;
+    desc_load(knn, dv);
+    // the descriptor load must stay older than both sets' loads (the waits
+    // below count on it): no instruction moves across this point
+    __builtin_amdgcn_sched_barrier(0);
+    SegPlan prev = cur;
+    const __amdgpu_buffer_rsrc_t rkeys = make_rsrc(keys, (uint64_t)nkeys * sizeof(K));
+    const __amdgpu_buffer_rsrc_t rpay = make_rsrc(PAY ? pay : nullptr, PAY ? (uint64_t)nkeys * 4 : 0);
+    auto load = [&](const SegPlan& p, u32x4 (&rk)[RS], u32x4 (&rp)[R]) {
+        if constexpr (WHOLE) prefetch_whole<K, PAY, L, R>(p, rkeys, rpay, rk, rp);
+        else prefetch_split<K, L, RS>(p, keys, (uint64_t)nkeys, rk);
+    };
+    load(cur, rkA, rpA);
+    load(nxt, rkB, rpB);
+    auto step = [&](u32x4 (&rk)[RS], u32x4 (&rp)[R]) {
+        __builtin_amdgcn_s_setprio(2);
+        wait_vm<PAY ? 2 * R : RS>();
+        if constexpr (WHOLE) commit<K, PAY, L, R>(cur, rk, rp, sp.sKey, sp.sPay);
+        else commit_split<K, L, RS>(cur, rk, sp.sKey);
+        __syncthreads();
+        if (kcur > lo) write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+        // the descriptors loaded a step ago have landed (the wait above)
+        const PackGroup gn = group_from(dv, knn);
+        desc_load(gn.next, dv);
+        __builtin_amdgcn_sched_barrier(0);
+        const SegPlan nn = make_plan<K, PAY>(gn.d);
+        load(nn, rk, rp);
+        __builtin_amdgcn_s_setprio(0);
+        if (cur.s > 0)
+            merge_lanes<K, PAY, L, (!PAY || R <= 3)>(cur, sp.sKey, sp.sPay, sp.sOut, sp.sIdx,
+                                                    sp.sXb, sp.sYb);
+        prev = cur;
+        cur = nxt;
+        nxt = nn;
+        kcur = knxt;
+        knxt = knn;
+        knn = gn.next;
+    };
+    // steps in pairs, so that the sets alternate A, B, A, ... with no exit
+    // between them; a step past the stretch is empty (its loads read nothing,
+    // it merges nothing, and its write-back is the last real step's)
+    do {
+        step(rkA, rpA);
+        step(rkB, rpB);
+    } while (kcur < hi);
+    write_back<K, PAY, L, R>(prev, sp.sOut, sp.sIdx, out, out_pay);
+}
+
 // The same with two subproblems in flight: while the workgroup merges
 // subproblem w, the loads of w + G and w + 2G (its next two) are in flight
 // in two register sets, so every load has two merges' time to land.  Per
@@ -138,11 +339,19 @@ __global__ __launch_bounds__(L) void merge_persistent_kernel(
 // WHOLE: the arrays are below 4 GiB and one buffer resource spans each;
 // otherwise (keys only) every window gets a resource of its own and the
 // register sets one more slot (prefetch_split).
-template <typename K, bool PAY, int L, int R, bool WHOLE>
+//
+// PACK: the workgroup takes the contiguous stretch [P g / G, P (g + 1) / G)
+// of an output-ordered list and merges it in packed steps (see pack_group).
+template <typename K, bool PAY, int L, int R, bool WHOLE, bool PACK>
 __device__ __forceinline__ void merge_pipelined(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
     const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
+    if constexpr (PACK) {
+        merge_pipelined_packed<K, PAY, L, R, WHOLE>(keys, pay, nkeys, out, out_pay, nout, desc, P,
+                                                    P_dev, cap);
+        return;
+    }
     extern __shared__ __align__(16) char smem[];
     const SmemPtrs<K, PAY, L> sp(smem, cap);
     if (P_dev) {
@@ -247,20 +456,22 @@ __device__ __forceinline__ void merge_pipelined(
 // Four waves per SIMD need at most 128 registers per lane: four workgroups
 // per compute unit then fit both registers and LDS.  64-bit keys with
 // payloads need more (the wide form, three workgroups).
-template <typename K, bool PAY, int L, int R, bool WHOLE>
+template <typename K, bool PAY, int L, int R, bool WHOLE, bool PACK>
 __global__ __launch_bounds__(L) __attribute__((amdgpu_waves_per_eu(4))) void merge_pipelined_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
     const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
-    merge_pipelined<K, PAY, L, R, WHOLE>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
+    merge_pipelined<K, PAY, L, R, WHOLE, PACK>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev,
+                                               cap);
 }
 
-template <typename K, bool PAY, int L, int R, bool WHOLE>
+template <typename K, bool PAY, int L, int R, bool WHOLE, bool PACK>
 __global__ __launch_bounds__(L) void merge_pipelined_wide_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t nkeys,
     K* __restrict__ out, uint32_t* __restrict__ out_pay, int64_t nout,
     const PieceDesc* __restrict__ desc, int64_t P, const int64_t* __restrict__ P_dev, uint32_t cap) {
-    merge_pipelined<K, PAY, L, R, WHOLE>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap);
+    merge_pipelined<K, PAY, L, R, WHOLE, PACK>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev,
+                                               cap);
 }
 
 // One workgroup per subproblem, staged straight into LDS; for subproblems
@@ -581,7 +792,8 @@ static bool fits_regs(uint32_t cap, int R) {
 template <typename K, bool PAY, int R>
 static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t nkeys, K* out,
                                     uint32_t* out_pay, int64_t nout, const PieceDesc* desc,
-                                    int64_t P, const int64_t* P_dev, uint32_t cap, hipStream_t st) {
+                                    int64_t P, const int64_t* P_dev, uint32_t cap, bool packed,
+                                    hipStream_t st) {
     constexpr int L = kMergeThreads;
     // two register sets in flight where they fit the register budget; one
     // buffer resource spans each array below 4 GiB, larger arrays take one
@@ -600,15 +812,22 @@ static hipError_t launch_persistent(const K* keys, const uint32_t* pay, int64_t 
                                                  P_dev, cap);
             return hipGetLastError();
         };
-        static std::atomic<bool> attr2{false}, attr3{false};
-        static std::atomic<uint64_t> occ2{0}, occ3{0};
+        static std::atomic<bool> attr2{false}, attr3{false}, attr4{false}, attr5{false};
+        static std::atomic<uint64_t> occ2{0}, occ3{0}, occ4{0}, occ5{0};
         if constexpr (sizeof(K) == 8 && PAY) {
-            if (whole) return go(merge_pipelined_wide_kernel<K, PAY, L, R, true>, attr2, occ2);
+            if (whole) return go(merge_pipelined_wide_kernel<K, PAY, L, R, true, false>, attr2, occ2);
+        } else if constexpr (PAY && R > 3) {
+            if (whole) return go(merge_pipelined_kernel<K, PAY, L, R, true, false>, attr2, occ2);
         } else if constexpr (PAY) {
-            if (whole) return go(merge_pipelined_kernel<K, PAY, L, R, true>, attr2, occ2);
+            if (whole)
+                return packed ? go(merge_pipelined_kernel<K, PAY, L, R, true, true>, attr4, occ4)
+                              : go(merge_pipelined_kernel<K, PAY, L, R, true, false>, attr2, occ2);
         } else {
-            return whole ? go(merge_pipelined_kernel<K, PAY, L, R, true>, attr2, occ2)
-                         : go(merge_pipelined_kernel<K, PAY, L, R, false>, attr3, occ3);
+            if (packed)
+                return whole ? go(merge_pipelined_kernel<K, PAY, L, R, true, true>, attr4, occ4)
+                             : go(merge_pipelined_kernel<K, PAY, L, R, false, true>, attr5, occ5);
+            return whole ? go(merge_pipelined_kernel<K, PAY, L, R, true, false>, attr2, occ2)
+                         : go(merge_pipelined_kernel<K, PAY, L, R, false, false>, attr3, occ3);
         }
     }
     auto kern = merge_persistent_kernel<K, PAY, L, R>;
@@ -629,7 +848,7 @@ template <typename K, bool PAY>
 static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_t nkeys,
                                  void* out_v, uint32_t* out_pay, int64_t nout,
                                  const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
-                                 hipStream_t st) {
+                                 bool packed, hipStream_t st) {
     const K* keys = static_cast<const K*>(keys_v);
     K* out = static_cast<K*>(out_v);
     if (P <= 0) return hipSuccess;
@@ -638,14 +857,14 @@ static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_
     if constexpr (PAY && sizeof(K) == 4) {
         if (fits_regs<K, PAY>(cap, 3))
             return launch_persistent<K, PAY, 3>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev,
-                                                cap, st);
+                                                cap, packed, st);
     }
     if (fits_regs<K, PAY>(cap, 5))
         return launch_persistent<K, PAY, 5>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap,
-                                            st);
+                                            packed, st);
     if (fits_regs<K, PAY>(cap, 9))
         return launch_persistent<K, PAY, 9>(keys, pay, nkeys, out, out_pay, nout, desc, P, P_dev, cap,
-                                            st);
+                                            false, st);
     constexpr int L = kMergeThreads;
     auto kern = merge_direct_kernel<K, PAY, L>;
     static std::atomic<bool> attr{false};
@@ -670,14 +889,14 @@ hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const in
 hipError_t launch_merge_desc(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
                              void* out_keys, uint32_t* out_pay, int64_t nout,
                              const PieceDesc* desc, int64_t P, const int64_t* P_dev, uint32_t cap,
-                             hipStream_t st) {
+                             hipStream_t st, bool packed) {
     hipError_t e = hipSuccess;
     with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         e = pay ? launch_merge_t<K, true>(keys, pay, nkeys, out_keys, out_pay, nout, desc, P, P_dev,
-                                          cap, st)
+                                          cap, packed, st)
                 : launch_merge_t<K, false>(keys, nullptr, nkeys, out_keys, nullptr, nout, desc, P,
-                                           P_dev, cap, st);
+                                           P_dev, cap, packed, st);
     });
     return e;
 }
