@@ -213,7 +213,8 @@ int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t*
     if (e != hipSuccess) return hip_fail(e, "cases launch");
     if (!pl.hier)
         e = sm::launch_merge_desc(dtype, keys, payloads, n + m, out_keys, out_payloads, n + m, desc,
-                                  P, nullptr, pl.cap, st, /*packed=*/true);
+                                  P, nullptr, sm::merge_pack_cap(dtype, payloads != nullptr, pl.cap),
+                                  st, /*packed=*/true);
     else
         e = sm::launch_batch(dtype, keys, payloads, n + m, out_keys, out_payloads, n + m, desc, P,
                              pl.tile, tail + (pl.off_batch - pl.off_desc), pl.layout, st);

@@ -253,7 +253,9 @@ __global__ __launch_bounds__(256) void batch_cases_kernel(
         int64_t np, ns, p_a, p_b;
         job_counts(j, tile, cap, np, ns, p_a, p_b);
         if (np == 1) {
-            desc[w] = j;
+            PieceDesc d = j;
+            d.b_f |= kFirstBit;
+            desc[w] = d;
             continue;
         }
         const int64_t a = desc_a(j), b = desc_b(j);
@@ -263,6 +265,20 @@ __global__ __launch_bounds__(256) void batch_cases_kernel(
         const int64_t v = w - pstart[k];
         const Piece<int64_t> pc = v < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, v)
                                           : step4_piece<int64_t>(BA, BB, xbar, ybar, v - p_a);
+        // the job's subproblems in output order (as cases_kernel orders a
+        // single merge's), the first one marked
+        const int64_t ne_a = a > 0 ? BA.of(a - 1) + 1 : 0, ne_b = b > 0 ? BB.of(b - 1) + 1 : 0;
+        auto starts_below = [](const Blocks<int64_t>& Bk, int64_t x) {
+            return x <= 0 ? (int64_t)0 : Bk.of(x - 1) + 1;
+        };
+        int64_t place;
+        if (v < p_a) {
+            place = v < ne_a ? v + starts_below(BB, xbar[v] < b ? xbar[v] : b) : ne_b + v;
+        } else {
+            const int64_t u = v - p_a;
+            place = u < ne_b ? u + starts_below(BA, ybar[u] < a ? ybar[u] : a) : p_a + u;
+        }
+        if (place < 0 || place >= np) place = v;   // inputs that are not sorted
         PieceDesc d;
         d.ka0 = j.ka0 + pc.a_lo;
         d.kb0 = j.kb0 + pc.b_lo;
@@ -276,7 +292,8 @@ __global__ __launch_bounds__(256) void batch_cases_kernel(
             d.a_f = (uint32_t)(pc.a_hi - pc.a_lo) | (sa ? kSuccBit : 0u);
             d.b_f = (uint32_t)(pc.b_hi - pc.b_lo) | (sb ? kSuccBit : 0u);
         }
-        desc[w] = d;
+        if (place == 0) d.b_f |= kFirstBit;
+        desc[pstart[k] + place] = d;
     }
 }
 
@@ -428,7 +445,7 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
                                                      ranks, L.p_max, desc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_merge_desc(dtype, keys, pay, nkeys, out_keys, out_pay, nout, desc, L.p_max,
-                             totals, cap, st);
+                             totals, merge_pack_cap(dtype, pay != nullptr, cap), st, /*packed=*/true);
 }
 
 }  // namespace sm

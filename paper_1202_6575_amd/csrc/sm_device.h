@@ -211,6 +211,11 @@ __device__ __forceinline__ u32x4 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t b
 // Bit 31 of a_f (b_f) is set when keys[ka0 + a] (keys[kb0 + b]) is the next
 // element of the same source array, i.e. the segment's successor exists.
 // Written by the case-selection kernel (Steps 3-4), read by the merge kernel.
+// Jobs of the batch engine (whole merges) use the same record; a job's
+// lengths may reach 2^30.  In a subproblem, whose lengths stay below the
+// merge capacity, bit 30 of b_f marks the first subproblem of a merge in a
+// list that holds several independent merges: packed steps never join
+// across it.
 // ---------------------------------------------------------------------------
 struct PieceDesc {
     int64_t ka0, kb0, out0;
@@ -218,8 +223,17 @@ struct PieceDesc {
 };
 static_assert(sizeof(PieceDesc) == 32, "descriptors are read as two 16-byte chunks");
 constexpr uint32_t kSuccBit = 0x80000000u;
+constexpr uint32_t kFirstBit = 0x40000000u;
+// lengths of a job
 __host__ __device__ inline int desc_a(const PieceDesc& d) { return (int)(d.a_f & ~kSuccBit); }
 __host__ __device__ inline int desc_b(const PieceDesc& d) { return (int)(d.b_f & ~kSuccBit); }
+// lengths of a subproblem
+__host__ __device__ inline int piece_a(const PieceDesc& d) {
+    return (int)(d.a_f & ~(kSuccBit | kFirstBit));
+}
+__host__ __device__ inline int piece_b(const PieceDesc& d) {
+    return (int)(d.b_f & ~(kSuccBit | kFirstBit));
+}
 
 template <typename K>
 struct Vec { static constexpr int N = 16 / sizeof(K); };
@@ -387,8 +401,8 @@ template <typename K, bool PAY>
 __device__ __forceinline__ SegPlan make_plan(const PieceDesc& d) {
     constexpr int V = Vec<K>::N;
     SegPlan p;
-    p.a = desc_a(d);
-    p.b = desc_b(d);
+    p.a = piece_a(d);
+    p.b = piece_b(d);
     p.s = p.a + p.b;
     p.succA = (d.a_f & kSuccBit) != 0;
     p.succB = (d.b_f & kSuccBit) != 0;
@@ -938,7 +952,7 @@ struct SmemPtrs {
 // A descriptor is usable if it lies inside the arrays and fits the LDS.
 __device__ __forceinline__ bool desc_ok(const PieceDesc& d, int64_t nkeys, int64_t nout,
                                         uint32_t cap) {
-    const int64_t a = desc_a(d), b = desc_b(d);
+    const int64_t a = piece_a(d), b = piece_b(d);
     return a + b <= (int64_t)cap && d.ka0 >= 0 && d.ka0 + a <= nkeys && d.kb0 >= 0 &&
            d.kb0 + b <= nkeys && d.out0 >= 0 && d.out0 + a + b <= nout;
 }

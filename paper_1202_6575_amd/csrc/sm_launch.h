@@ -51,6 +51,11 @@ constexpr uint32_t kFineCap = 64;
 // key type, in the register-pipelined kernel at the default tile.
 uint32_t merge_cap_for_tile(int32_t tile);
 
+// Capacity for packed steps over subproblems of at most `cap` elements: the
+// largest that keeps the merge workgroup's LDS granules and register slots
+// (and so the workgroups per compute unit) as they are for `cap`.
+uint32_t merge_pack_cap(int dtype, bool pay, uint32_t cap);
+
 // Number of compute units of the current device.
 int device_cu_count();
 

@@ -180,20 +180,21 @@ __device__ __forceinline__ PackGroup pack_group(const PieceDesc (&d)[kPackMax], 
     if (!desc_ok(d[0], nkeys, nout, cap)) return g;
     // the union's ends so far (fixed indices only: a runtime index into d
     // would move the array to memory)
-    int64_t ea = d[0].ka0 + desc_a(d[0]), eb = d[0].kb0 + desc_b(d[0]);
-    int64_t ec = d[0].out0 + desc_a(d[0]) + desc_b(d[0]);
+    int64_t ea = d[0].ka0 + piece_a(d[0]), eb = d[0].kb0 + piece_b(d[0]);
+    int64_t ec = d[0].out0 + piece_a(d[0]) + piece_b(d[0]);
     uint32_t sa = d[0].a_f & kSuccBit, sb = d[0].b_f & kSuccBit;
     int cnt = 1;
     bool open = true;
 #pragma unroll
     for (int t = 1; t < kPackMax; ++t) {
         const PieceDesc& e = d[t];
-        const int64_t ee = e.out0 + desc_a(e) + desc_b(e);
-        const bool ok = open && t < avail && desc_ok(e, nkeys, nout, cap) && e.ka0 == ea &&
-                        e.kb0 == eb && e.out0 == ec && ee - d[0].out0 <= (int64_t)cap;
+        const int64_t ee = e.out0 + piece_a(e) + piece_b(e);
+        const bool ok = open && t < avail && !(e.b_f & kFirstBit) && desc_ok(e, nkeys, nout, cap) &&
+                        e.ka0 == ea && e.kb0 == eb && e.out0 == ec &&
+                        ee - d[0].out0 <= (int64_t)cap;
         if (ok) {
-            ea = e.ka0 + desc_a(e);
-            eb = e.kb0 + desc_b(e);
+            ea = e.ka0 + piece_a(e);
+            eb = e.kb0 + piece_b(e);
             ec = ee;
             sa = e.a_f & kSuccBit;
             sb = e.b_f & kSuccBit;
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(L) void merge_direct_kernel(
     const SmemPtrs<K, PAY, L> sp(smem, cap);
     if (P_dev && (int64_t)blockIdx.x >= *P_dev) return;
     const PieceDesc d = desc[blockIdx.x];
-    if (!desc_ok(d, nkeys, nout, cap) || desc_a(d) + desc_b(d) == 0) return;
+    if (!desc_ok(d, nkeys, nout, cap) || piece_a(d) + piece_b(d) == 0) return;
     const SegPlan p = make_plan<K, PAY>(d);
     stage_direct<K, PAY, L>(p, keys, (uint64_t)nkeys, pay, sp.sKey, sp.sPay);
     __syncthreads();
@@ -878,6 +879,34 @@ static hipError_t launch_merge_t(const void* keys_v, const uint32_t* pay, int64_
 }
 
 uint32_t merge_cap_for_tile(int32_t tile) { return 2u * (uint32_t)tile; }
+
+// Register slots the pipelined merge uses for a capacity (as launch_merge_t
+// picks them); 0 for the unpipelined forms.
+template <typename K, bool PAY>
+static int merge_regs(uint32_t cap) {
+    if (PAY && sizeof(K) == 4 && fits_regs<K, PAY>(cap, 3)) return 3;
+    if (fits_regs<K, PAY>(cap, 5)) return 5;
+    return fits_regs<K, PAY>(cap, 9) ? 9 : 0;
+}
+
+uint32_t merge_pack_cap(int dtype, bool pay, uint32_t cap) {
+    uint32_t best = cap;
+    with_key_type_asc(dtype, [&](auto z) {
+        using K = decltype(z);
+        auto regs = [&](uint32_t c) { return pay ? merge_regs<K, true>(c) : merge_regs<K, false>(c); };
+        auto lds = [&](uint32_t c) {
+            return pay ? MergeSmem<K, true, kMergeThreads>::bytes(c)
+                       : MergeSmem<K, false, kMergeThreads>::bytes(c);
+        };
+        auto granules = [&](uint32_t c) { return (lds(c) + kLdsGranule - 1) / kLdsGranule; };
+        const int r0 = regs(cap);
+        const uint32_t g0 = granules(cap);
+        if (r0 == 0 || r0 == 9) return;
+        for (uint32_t c = cap + 8; c <= 2 * cap && regs(c) == r0 && granules(c) == g0; c += 8)
+            best = c;
+    });
+    return best;
+}
 
 hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                         const int64_t* ybar, PieceDesc* desc, hipStream_t st) {
