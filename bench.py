@@ -143,7 +143,8 @@ def _pmc_by_kernel(run_dir: str, counter: str):
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] != counter:
                 continue
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+            name = name.replace("void ", "")
             v = acc.setdefault(name, [0.0, 0])
             v[0] += float(r["Counter_Value"])
             v[1] += 1
