@@ -39,8 +39,9 @@ __device__ __forceinline__ void job_counts(const PieceDesc& j, int64_t tile, uin
         p_a = p_b = 0;
         return;
     }
-    p_a = a > 0 ? (a + tile - 1) / tile : 1;
-    p_b = b > 0 ? (b + tile - 1) / tile : 1;
+    const double rt = 1.0 / (double)tile;
+    p_a = a > 0 ? RcpBlocks::div(a + tile - 1, tile, rt) : 1;
+    p_b = b > 0 ? RcpBlocks::div(b + tile - 1, tile, rt) : 1;
     pieces = p_a + p_b;
     splitters = p_a + p_b + 2;
 }
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void batch_partition_kernel(
         const int64_t u = s - sstart[k];
         int64_t r;
         if (u <= p_a) {
-            const int64_t xu = Blocks<int64_t>(a, p_a).start(u);
+            const int64_t xu = RcpBlocks(a, p_a).start(u);
             if (xu >= a) r = b;
             else if (model) {
                 r = learned_rank<false, K>(B, b, A[xu], model, step_frac, n_probe);
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(256) void batch_partition_kernel(
             } else r = rank_low<K, int64_t>(B, b, A[xu]);
         } else {
             const int64_t v = u - (p_a + 1);
-            const int64_t yv = Blocks<int64_t>(b, p_b).start(v);
+            const int64_t yv = RcpBlocks(b, p_b).start(v);
             if (yv >= b) r = a;
             else if (model) {
                 r = learned_rank<true, K>(A, a, B[yv], model, step_frac, n_probe);
@@ -261,14 +262,14 @@ __global__ __launch_bounds__(256) void batch_cases_kernel(
         const int64_t a = desc_a(j), b = desc_b(j);
         const int64_t* xbar = ranks + sstart[k];
         const int64_t* ybar = xbar + (p_a + 1);
-        const Blocks<int64_t> BA(a, p_a), BB(b, p_b);
+        const RcpBlocks BA(a, p_a), BB(b, p_b);
         const int64_t v = w - pstart[k];
         const Piece<int64_t> pc = v < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, v)
                                           : step4_piece<int64_t>(BA, BB, xbar, ybar, v - p_a);
         // the job's subproblems in output order (as cases_kernel orders a
         // single merge's), the first one marked
         const int64_t ne_a = a > 0 ? BA.of(a - 1) + 1 : 0, ne_b = b > 0 ? BB.of(b - 1) + 1 : 0;
-        auto starts_below = [](const Blocks<int64_t>& Bk, int64_t x) {
+        auto starts_below = [](const RcpBlocks& Bk, int64_t x) {
             return x <= 0 ? (int64_t)0 : Bk.of(x - 1) + 1;
         };
         int64_t place;

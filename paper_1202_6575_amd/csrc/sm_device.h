@@ -39,6 +39,41 @@ struct Blocks {
     }
 };
 
+// The same decomposition with the divisions done as products with
+// double-precision reciprocals (exact after one correction step for
+// positions below 2^50): 64-bit integer division is a long instruction
+// sequence on this hardware, and kernels that place hundreds of thousands
+// of blocks would spend their time there.  Built on the host (and passed
+// to a kernel) or in a kernel (one per job of a batch); both give the same
+// values.
+struct RcpBlocks {
+    int64_t len, p, q, r, c, rc;
+    double rcp_c, rcp_q;
+    __host__ __device__ RcpBlocks(int64_t len_, int64_t p_) : len(len_), p(p_) {
+        q = p > 0 ? div(len, p, 1.0 / (double)p) : 0;
+        r = len - q * p;
+        c = q + (r != 0);
+        rc = r * c;
+        rcp_c = c > 0 ? 1.0 / (double)c : 0.0;
+        rcp_q = q > 0 ? 1.0 / (double)q : 0.0;
+    }
+    __device__ int64_t start(int64_t i) const {
+        if (i >= p) return len;
+        return i < r ? i * c : i * q + r;
+    }
+    // k / d for 0 <= k < 2^50, d >= 1, rd = 1 / d
+    __host__ __device__ static int64_t div(int64_t k, int64_t d, double rd) {
+        int64_t x = (int64_t)((double)k * rd);
+        const int64_t rem = k - x * d;
+        x += (rem >= d) - (rem < 0);
+        return x;
+    }
+    __device__ int64_t of(int64_t k) const {
+        if (k >= len) return p;
+        return k < rc ? div(k, c, rcp_c) : div(k - rc, q, rcp_q) + r;
+    }
+};
+
 // Quotient k / d for 0 <= k < 2^22 and a workgroup-uniform divisor d >= 1
 // with rd ~ 1 / d (hardware reciprocal, within an ulp): the float product is
 // within one of the quotient, and one exact correction step fixes it.

@@ -46,18 +46,18 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ ke
 // subproblem of B block j has place j + #{i : x_i < ybar_j}.  Blocks that
 // start at the end of their array (more blocks than elements) hold empty
 // subproblems; they take the places after all others, A's first.
-__global__ __launch_bounds__(256) void cases_kernel(int64_t n, int64_t m, int64_t p_a,
-                                                    int64_t p_b, const int64_t* __restrict__ xbar,
+__global__ __launch_bounds__(256) void cases_kernel(RcpBlocks BA, RcpBlocks BB,
+                                                    const int64_t* __restrict__ xbar,
                                                     const int64_t* __restrict__ ybar,
                                                     PieceDesc* __restrict__ desc) {
+    const int64_t n = BA.len, m = BB.len, p_a = BA.p, p_b = BB.p;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= p_a + p_b) return;
-    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
     const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
                                       : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
     // blocks that hold an element; block starts below x (x <= len)
     const int64_t ne_a = n > 0 ? BA.of(n - 1) + 1 : 0, ne_b = m > 0 ? BB.of(m - 1) + 1 : 0;
-    auto starts_below = [](const Blocks<int64_t>& Bk, int64_t x) {
+    auto starts_below = [](const RcpBlocks& Bk, int64_t x) {
         return x <= 0 ? (int64_t)0 : Bk.of(x - 1) + 1;
     };
     int64_t place;
@@ -911,7 +911,8 @@ uint32_t merge_pack_cap(int dtype, bool pay, uint32_t cap) {
 hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                         const int64_t* ybar, PieceDesc* desc, hipStream_t st) {
     const int64_t P = p_a + p_b;
-    cases_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(n, m, p_a, p_b, xbar, ybar, desc);
+    cases_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(RcpBlocks(n, p_a), RcpBlocks(m, p_b),
+                                                              xbar, ybar, desc);
     return hipGetLastError();
 }
 
