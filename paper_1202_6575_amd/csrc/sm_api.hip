@@ -209,6 +209,13 @@ int cases_and_merge(const Plan& pl, int dtype, const void* keys, const uint32_t*
         if (e != hipSuccess) return hip_fail(e, "merge launch");
         return SM_OK;
     }
+    // a few large subproblems: Steps 3-4 inside the merge workgroups
+    if (!pl.hier && sm::merge_cases_direct_applies(dtype, payloads != nullptr, pl.cap, P)) {
+        e = sm::launch_merge_cases_direct(dtype, keys, payloads, n, m, pl.p_a, pl.p_b, xbar, ybar,
+                                          out_keys, out_payloads, pl.cap, st);
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+        return SM_OK;
+    }
     e = sm::launch_cases(n, m, pl.p_a, pl.p_b, xbar, ybar, desc, st);
     if (e != hipSuccess) return hip_fail(e, "cases launch");
     if (!pl.hier)

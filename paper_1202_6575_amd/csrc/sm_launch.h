@@ -25,7 +25,31 @@ hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m,
                             int64_t p_a, int64_t p_b, int64_t* xbar, int64_t* ybar,
                             hipStream_t st);
 
+// Block starts up to which Steps 1-2 run as group searches, kSearchGroup
+// lanes per search.
+constexpr int64_t kGroupSearchMax = 2048;
+constexpr int kSearchGroup = 16;
+
 struct PieceDesc;
+
+// Workgroup size of the merge that takes its subproblem straight from the
+// cross ranks (a few large subproblems), and the subproblem count, per
+// compute unit, up to which it is used.
+constexpr int kWideMergeThreads = 1024;
+constexpr int kWideMergeMaxWgPerCu = 4;
+
+// Whether launch_merge_cases_direct serves P subproblems of up to cap
+// elements: few of them (at most kWideMergeMaxWgPerCu per compute unit),
+// each larger than the register-pipelined merges stage or fewer than the
+// compute units, within one workgroup's LDS.
+bool merge_cases_direct_applies(int dtype, bool pay, uint32_t cap, int64_t P);
+
+// Steps 3-4 and the merges in one launch, one kWideMergeThreads workgroup per
+// subproblem (each computes its own descriptor from xbar / ybar).
+hipError_t launch_merge_cases_direct(int dtype, const void* keys, const uint32_t* pay, int64_t n,
+                                     int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
+                                     const int64_t* ybar, void* out_keys, uint32_t* out_pay,
+                                     uint32_t cap, hipStream_t st);
 
 // Steps 3-4 case selection alone.
 hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,

@@ -33,6 +33,84 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ ke
     }
 }
 
+// Steps 1-2 for a few block starts, where the dependent loads of the
+// searches, not their traffic, set the time: G lanes share one search and
+// probe G evenly spaced elements per round, which leaves an interval 1/G as
+// long, so a rank over len elements takes about log_G(len) rounds of loads
+// instead of log2(len).  The ranks are those of partition_kernel (the same
+// definitions, rank_low for A block starts and rank_high for B's).
+template <typename K, int G>
+__global__ __launch_bounds__(256) void partition_group_kernel(const K* __restrict__ keys,
+                                                              int64_t n, int64_t m, int64_t p_a,
+                                                              int64_t p_b,
+                                                              int64_t* __restrict__ xbar,
+                                                              int64_t* __restrict__ ybar) {
+    static_assert(G >= 2 && G <= 64 && 64 % G == 0, "a search group lies inside one wave");
+    const int64_t qy = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int g = (int)(threadIdx.x % G);
+    const int first = (int)(threadIdx.x & 63) - g;   // the group's first lane in the wave
+    // every branch below is taken by whole groups
+    if (qy > p_a + 1 + p_b) return;
+    const bool low = qy <= p_a;   // an A block start searched in B
+    const int64_t j = qy - (p_a + 1);
+    const int64_t start = low ? RcpBlocks(n, p_a).start(qy) : RcpBlocks(m, p_b).start(j);
+    const int64_t own = low ? n : m, len = low ? m : n;
+    int64_t lo = len;
+    if (start < own) {
+        const K x = keys[low ? start : n + start];
+        const K* S = low ? keys + n : keys;
+        int64_t hi = len;
+        lo = 0;
+        // [lo, hi) holds the elements not yet compared; the rank is in [lo, hi]
+        while (lo < hi) {
+            const int64_t step = (hi - lo + G - 1) / G;
+            const int64_t e = lo + (int64_t)(g + 1) * step - 1;
+            bool below = false;   // S[e] counts towards the rank
+            if (e < hi) {
+                const K v = S[e];
+                below = low ? v < x : !(x < v);
+            }
+            // the probes that count form a prefix of the group's lanes
+            const uint64_t bits = (__ballot(below) >> first) & (G == 64 ? ~0ull : (1ull << G) - 1);
+            const int c = __popcll(bits);
+            lo += (int64_t)c * step;
+            // probe c (if there is one) did not count: the rank is at most its index
+            const int64_t ec = lo + step - 1;
+            if (c < G && ec < hi) hi = ec;
+        }
+    }
+    if (g == 0) {
+        if (low) xbar[qy] = lo;
+        else ybar[j] = lo;
+    }
+}
+
+// Steps 3-4 of subproblem w (A block w for w < p_a, else B block w - p_a)
+// as a descriptor: the five cases in two-select form.
+__device__ __forceinline__ PieceDesc case_desc(const RcpBlocks& BA, const RcpBlocks& BB,
+                                               const int64_t* __restrict__ xbar,
+                                               const int64_t* __restrict__ ybar, int64_t w) {
+    const int64_t n = BA.len, m = BB.len, p_a = BA.p;
+    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
+                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
+    PieceDesc d;
+    d.ka0 = pc.a_lo;
+    d.kb0 = n + pc.b_lo;
+    d.out0 = pc.a_lo + pc.b_lo;
+    // a subproblem outside the arrays would be a bug: it is emptied, so the
+    // merge kernel never writes outside C (the output is then wrong, not unsafe)
+    if (!(0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= n && 0 <= pc.b_lo &&
+          pc.b_lo <= pc.b_hi && pc.b_hi <= m && pc.a_hi - pc.a_lo < (1 << 30) &&
+          pc.b_hi - pc.b_lo < (1 << 30))) {
+        d.a_f = 0;
+        d.b_f = 0;
+    } else {
+        d.a_f = (uint32_t)(pc.a_hi - pc.a_lo) | (pc.a_hi < n ? kSuccBit : 0u);
+        d.b_f = (uint32_t)(pc.b_hi - pc.b_lo) | (pc.b_hi < m ? kSuccBit : 0u);
+    }
+    return d;
+}
+
 // Steps 3-4 case selection: one thread per subproblem writes its descriptor
 // (the five cases in two-select form).  Subproblems 0..p_a-1 belong to the
 // processing elements of A blocks (Step 3), p_a..p_a+p_b-1 to B blocks
@@ -53,8 +131,6 @@ __global__ __launch_bounds__(256) void cases_kernel(RcpBlocks BA, RcpBlocks BB,
     const int64_t n = BA.len, m = BB.len, p_a = BA.p, p_b = BB.p;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= p_a + p_b) return;
-    const Piece<int64_t> pc = w < p_a ? step3_piece<int64_t>(BA, BB, xbar, ybar, w)
-                                      : step4_piece<int64_t>(BA, BB, xbar, ybar, w - p_a);
     // blocks that hold an element; block starts below x (x <= len)
     const int64_t ne_a = n > 0 ? BA.of(n - 1) + 1 : 0, ne_b = m > 0 ? BB.of(m - 1) + 1 : 0;
     auto starts_below = [](const RcpBlocks& Bk, int64_t x) {
@@ -70,22 +146,7 @@ __global__ __launch_bounds__(256) void cases_kernel(RcpBlocks BA, RcpBlocks BB,
     // out of range only for inputs that are not sorted (the subproblems then
     // overlap); the merge kernel checks every descriptor it reads
     if (place < 0 || place >= p_a + p_b) place = w;
-    PieceDesc d;
-    d.ka0 = pc.a_lo;
-    d.kb0 = n + pc.b_lo;
-    d.out0 = pc.a_lo + pc.b_lo;
-    // a subproblem outside the arrays would be a bug: it is emptied, so the
-    // merge kernel never writes outside C (the output is then wrong, not unsafe)
-    if (!(0 <= pc.a_lo && pc.a_lo <= pc.a_hi && pc.a_hi <= n && 0 <= pc.b_lo &&
-          pc.b_lo <= pc.b_hi && pc.b_hi <= m && pc.a_hi - pc.a_lo < (1 << 30) &&
-          pc.b_hi - pc.b_lo < (1 << 30))) {
-        d.a_f = 0;
-        d.b_f = 0;
-    } else {
-        d.a_f = (uint32_t)(pc.a_hi - pc.a_lo) | (pc.a_hi < n ? kSuccBit : 0u);
-        d.b_f = (uint32_t)(pc.b_hi - pc.b_lo) | (pc.b_hi < m ? kSuccBit : 0u);
-    }
-    desc[place] = d;
+    desc[place] = case_desc(BA, BB, xbar, ybar, w);
 }
 
 // Persistent merge: workgroup g of G merges subproblems g, g + G, g + 2G, ...
@@ -494,6 +555,28 @@ __global__ __launch_bounds__(L) void merge_direct_kernel(
     write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
 }
 
+// Steps 3-4 and the merge of one subproblem per workgroup, for a few large
+// subproblems: the workgroup takes its descriptor from the cross ranks itself
+// (no descriptor pass) and runs L lanes, so that each lane's share stays
+// short and the compute unit holds enough waves to cover the latency of its
+// LDS reads.
+template <typename K, bool PAY, int L>
+__global__ __launch_bounds__(L) void merge_cases_direct_kernel(
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, RcpBlocks BA, RcpBlocks BB,
+    const int64_t* __restrict__ xbar, const int64_t* __restrict__ ybar, K* __restrict__ out,
+    uint32_t* __restrict__ out_pay, uint32_t cap) {
+    extern __shared__ __align__(16) char smem[];
+    const SmemPtrs<K, PAY, L> sp(smem, cap);
+    const int64_t nk = BA.len + BB.len;
+    const PieceDesc d = case_desc(BA, BB, xbar, ybar, blockIdx.x);
+    if (!desc_ok(d, nk, nk, cap) || piece_a(d) + piece_b(d) == 0) return;
+    const SegPlan p = make_plan<K, PAY>(d);
+    stage_direct<K, PAY, L>(p, keys, (uint64_t)nk, pay, sp.sKey, sp.sPay);
+    __syncthreads();
+    merge_lanes<K, PAY, L>(p, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
+    write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
+}
+
 // ---------------------------------------------------------------------------
 // Steps 3-4 for partitions into small blocks (subproblems of at most a few
 // dozen elements), without descriptors.
@@ -709,12 +792,20 @@ uint32_t merge_lds_bytes(int dtype, bool pay, uint32_t cap) {
 
 hipError_t launch_partition(int dtype, const void* keys, int64_t n, int64_t m, int64_t p_a,
                             int64_t p_b, int64_t* xbar, int64_t* ybar, hipStream_t st) {
-    const int64_t threads = p_a + p_b + 2;
+    const int64_t searches = p_a + p_b + 2;
+    // few searches: their rounds of dependent loads set the time, and a
+    // group of lanes per search takes fewer rounds (for more loads)
+    const bool group = searches <= kGroupSearchMax;
+    const int64_t threads = group ? searches * kSearchGroup : searches;
     const unsigned grid = (unsigned)((threads + 255) / 256);
     with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
-        partition_kernel<K><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), n, m, p_a, p_b,
-                                                  xbar, ybar);
+        if (group)
+            partition_group_kernel<K, kSearchGroup><<<grid, 256, 0, st>>>(
+                static_cast<const K*>(keys), n, m, p_a, p_b, xbar, ybar);
+        else
+            partition_kernel<K><<<grid, 256, 0, st>>>(static_cast<const K*>(keys), n, m, p_a, p_b,
+                                                      xbar, ybar);
     });
     return hipGetLastError();
 }
@@ -906,6 +997,52 @@ uint32_t merge_pack_cap(int dtype, bool pay, uint32_t cap) {
             best = c;
     });
     return best;
+}
+
+bool merge_cases_direct_applies(int dtype, bool pay, uint32_t cap, int64_t P) {
+    if (P <= 0 || P > (int64_t)kWideMergeMaxWgPerCu * device_cu_count()) return false;
+    bool ok = false;
+    with_key_type(dtype, [&](auto z) {
+        using K = decltype(z);
+        // subproblems past the register-pipelined kernels' reach (one
+        // 256-lane workgroup per compute unit there), or fewer subproblems
+        // than compute units
+        const bool big = pay ? merge_regs<K, true>(cap) >= 9 || merge_regs<K, true>(cap) == 0
+                             : merge_regs<K, false>(cap) >= 9 || merge_regs<K, false>(cap) == 0;
+        const uint32_t lds = pay ? MergeSmem<K, true, kWideMergeThreads>::bytes(cap)
+                                 : MergeSmem<K, false, kWideMergeThreads>::bytes(cap);
+        ok = (big || P <= device_cu_count()) && lds <= kMaxLds;
+    });
+    return ok;
+}
+
+hipError_t launch_merge_cases_direct(int dtype, const void* keys, const uint32_t* pay, int64_t n,
+                                     int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
+                                     const int64_t* ybar, void* out_keys, uint32_t* out_pay,
+                                     uint32_t cap, hipStream_t st) {
+    const int64_t P = p_a + p_b;
+    if (P <= 0) return hipSuccess;
+    constexpr int L = kWideMergeThreads;
+    hipError_t e = hipSuccess;
+    with_key_type(dtype, [&](auto z) {
+        using K = decltype(z);
+        auto go = [&](auto kern, std::atomic<bool>& attr, uint32_t lds) {
+            e = allow_big_lds_once(kern, attr);
+            if (e != hipSuccess) return;
+            kern<<<(unsigned)P, L, lds, st>>>(static_cast<const K*>(keys), pay, RcpBlocks(n, p_a),
+                                              RcpBlocks(m, p_b), xbar, ybar,
+                                              static_cast<K*>(out_keys), out_pay, cap);
+            e = hipGetLastError();
+        };
+        if (pay) {
+            static std::atomic<bool> attr{false};
+            go(merge_cases_direct_kernel<K, true, L>, attr, MergeSmem<K, true, L>::bytes(cap));
+        } else {
+            static std::atomic<bool> attr{false};
+            go(merge_cases_direct_kernel<K, false, L>, attr, MergeSmem<K, false, L>::bytes(cap));
+        }
+    });
+    return e;
 }
 
 hipError_t launch_cases(int64_t n, int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,

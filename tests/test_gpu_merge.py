@@ -69,6 +69,23 @@ def test_partition_matches_oracle(dtype):
         assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_partition_both_search_forms(dtype):
+    """Block counts on both sides of the switch between group searches (up
+    to 2048 block starts, 16 lanes per search) and one lane per search,
+    over empty, tiny, all-equal and long arrays."""
+    g = np.random.default_rng(83)
+    for n, m, alpha in [(0, 5000, 10), (5000, 0, 10), (3, 4, 2), (200_000, 150_000, 1 << 20),
+                        (100_000, 90_000, 1), (1_000_003, 7, 1000)]:
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        keys = dev(np.concatenate([A, B]))
+        for p_a, p_b in [(1, 1), (1023, 1023), (1024, 1023), (2000, 100), (5, 3000)]:
+            flush(f"partition forms dtype={np.dtype(dtype).name} n={n} m={m} p_a={p_a} p_b={p_b}")
+            xb, yb = sm.partition(keys, n, m, p_a, p_b)
+            rx, ry = oracle.cross_ranks(A, B, p_a, p_b)
+            assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
+
+
 def test_int32_1m_600k_partition_p256():
     """The config-1 arrays (int32 uniform in [0, 65536), n = 1e6, m = 6e5), p = 256."""
     A, B = datagen.uniform_pair(1_000_000, 600_000, 0, 65536, np.int32, seed=datagen.BASE_SEED)
@@ -131,6 +148,27 @@ def test_subproblem_sizes_across_kernels(dtype, with_pay):
         p = max(1, -(-len(A) // blk))
         flush(f"subproblem sizes dtype={np.dtype(dtype).name} pay={with_pay} block={blk} p={p}")
         check(A, B, with_pay, p_a=p, p_b=p)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_large_subproblems_few_and_many(dtype, with_pay):
+    """Subproblems too large for the register-pipelined merge: up to four
+    per compute unit they take the workgroups that select their own cases
+    (1024 lanes), past that the descriptor kernels (nine-chunk pipelined or
+    one workgroup per subproblem)."""
+    g = np.random.default_rng(90 + DTYPES.index(dtype) + 10 * with_pay)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    side_max = 2 * cus + 200
+    A0 = rand_sorted(g, 4700 * side_max, 5000, dtype)
+    B0 = rand_sorted(g, 4700 * side_max, 5000, dtype)
+    for blk in (3000, 4700):
+        for side in (1, 100, 2 * cus, side_max):
+            n = blk * side
+            A, B = A0[:n], B0[:n - 1]
+            flush(f"large subproblems dtype={np.dtype(dtype).name} pay={with_pay} block={blk} "
+                  f"p={side}")
+            check(A, B, with_pay, p_a=side, p_b=side)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
