@@ -825,6 +825,37 @@ __device__ __forceinline__ void lane_merge_checked(const K* sKey, K* sOut, uint3
 // together and lane blocks use select arithmetic (otherwise the searches run
 // one after the other and the block arithmetic branches, to stay within the
 // payload kernels' register budget).
+// Lane-level cross ranks (Steps 1-2 inside the workgroup) of a staged
+// subproblem: lane t writes xbar_t to sXb[t] and ybar_t to sYb[t], lane 0
+// also sXb[L] = b and sYb[L] = a; ends at a barrier.  The searches are short
+// chains of LDS reads that end at that barrier: they run above the merges
+// of other workgroups.
+template <typename K, int L, bool LEAN>
+__device__ __forceinline__ void lane_split(const SegPlan& p, const K* sKey,
+                                           const LaneBlocks<L, LEAN>& LA,
+                                           const LaneBlocks<L, LEAN>& LB, int* sXb, int* sYb) {
+    const int t = threadIdx.x;
+    const int a = p.a, b = p.b;
+    const int baseA = p.offA, baseB = p.wa + p.offB;
+    __builtin_amdgcn_s_setprio(1);
+    {
+        const int xt = LA.start(t), yt = LB.start(t);
+        // lanes without a block start search with the successor slot's key
+        // and discard the result
+        int rx, ry;
+        paired_bounds_any<K, LEAN>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
+                             sKey[baseB + (yt < b ? yt : b)], rx, ry);
+        sXb[t] = xt < a ? rx : b;
+        sYb[t] = yt < b ? ry : a;
+        if (t == 0) {
+            sXb[L] = b;
+            sYb[L] = a;
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
+}
+
 template <typename K, bool PAY, int L, bool LEAN = !PAY>
 __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, const uint32_t* sPay,
                                             K* sOut, uint32_t* sIdx, int* sXb, int* sYb) {
@@ -842,26 +873,8 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     const int dB = (p.waP + p.offPB) - (p.wa + p.offB);
 
     // ---- lane-level cross ranks (Steps 1-2 inside the workgroup) ----------
-    // (the searches are short chains of LDS reads that end at a barrier:
-    // they run above the merges of other workgroups)
-    __builtin_amdgcn_s_setprio(1);
     const LaneBlocks<L, LEAN> LA(a), LB(b);
-    {
-        const int xt = LA.start(t), yt = LB.start(t);
-        // lanes without a block start search with the successor slot's key
-        // and discard the result
-        int rx, ry;
-        paired_bounds_any<K, LEAN>(sKey + baseB, b, sKey[baseA + (xt < a ? xt : a)], sKey + baseA, a,
-                             sKey[baseB + (yt < b ? yt : b)], rx, ry);
-        sXb[t] = xt < a ? rx : b;
-        sYb[t] = yt < b ? ry : a;
-        if (t == 0) {
-            sXb[L] = b;
-            sYb[L] = a;
-        }
-    }
-    __syncthreads();
-    __builtin_amdgcn_s_setprio(0);
+    lane_split<K, L, LEAN>(p, sKey, LA, LB, sXb, sYb);
 
     // the sentinel loop is exact unless the A successor is the type maximum
     // and the B part holds that maximum too
@@ -897,6 +910,46 @@ __device__ __forceinline__ void merge_lanes(const SegPlan& p, const K* sKey, con
     }
     __syncthreads();
 
+}
+
+// Lane-level split and per-lane merges of a staged subproblem whose outputs
+// go straight to memory: output k to out[c0 + k] (and its payload to
+// out_pay[c0 + k]).  Each lane merges exactly its two pieces (no uniform
+// trip count, which would write past a piece), so no output buffer is
+// needed in LDS.  Entered after the barrier that follows staging; the
+// staging buffers may be reused only after a further barrier.
+template <typename K, bool PAY, int L>
+__device__ __forceinline__ void merge_lanes_to_memory(const SegPlan& p, const K* sKey,
+                                                      const uint32_t* sPay, int* sXb, int* sYb,
+                                                      K* out, uint32_t* out_pay) {
+    const int t = threadIdx.x;
+    const int a = p.a, b = p.b, s = p.s;
+    const int baseA = p.offA, baseB = p.wa + p.offB;
+    constexpr bool DIRECT = PAY && sizeof(K) == 4;
+    const int dPay = DIRECT ? (int)(sPay - reinterpret_cast<const uint32_t*>(sKey)) : 0;
+    const int dA = p.offPA - p.offA;
+    const int dB = (p.waP + p.offPB) - (p.wa + p.offB);
+    const LaneBlocks<L, true> LA(a), LB(b);
+    lane_split<K, L, true>(p, sKey, LA, LB, sXb, sYb);
+    const Piece<int> p3 = step3_piece<int>(LA, LB, sXb, sYb, t);
+    const Piece<int> p4 = step4_piece<int>(LA, LB, sXb, sYb, t);
+    auto valid = [&](const Piece<int>& q) {
+        return 0 <= q.a_lo && q.a_lo <= q.a_hi && q.a_hi <= a && 0 <= q.b_lo && q.b_lo <= q.b_hi &&
+               q.b_hi <= b && 0 <= q.c_off && q.c_off + (q.a_hi - q.a_lo) + (q.b_hi - q.b_lo) <= s;
+    };
+    const bool ok3 = valid(p3), ok4 = valid(p4);
+    // slot k of the merges' output indexing (offC / offCP + output index) is
+    // out[c0 - offC + k] (out_pay[c0 - offCP + k])
+    K* gOut = out + (p.c0 - p.offC);
+    uint32_t* gPay = PAY ? out_pay + (p.c0 - p.offCP) : nullptr;
+    lane_merge_checked<K, PAY, DIRECT>(sKey, gOut, gPay, dPay, sPay, dA, dB, baseA + p3.a_lo,
+                                       ok3 ? p3.a_hi - p3.a_lo : 0, baseB + p3.b_lo,
+                                       ok3 ? p3.b_hi - p3.b_lo : 0, p.offC + p3.c_off,
+                                       p.offCP + p3.c_off);
+    lane_merge_checked<K, PAY, DIRECT>(sKey, gOut, gPay, dPay, sPay, dA, dB, baseA + p4.a_lo,
+                                       ok4 ? p4.a_hi - p4.a_lo : 0, baseB + p4.b_lo,
+                                       ok4 ? p4.b_hi - p4.b_lo : 0, p.offC + p4.c_off,
+                                       p.offCP + p4.c_off);
 }
 
 // One output array of a subproblem, LDS -> HBM: aligned 16-byte stores for

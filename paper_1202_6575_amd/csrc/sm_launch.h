@@ -41,11 +41,12 @@ constexpr int kWideMergeMaxWgPerCu = 4;
 // Whether launch_merge_cases_direct serves P subproblems of up to cap
 // elements: few of them (at most kWideMergeMaxWgPerCu per compute unit),
 // each larger than the register-pipelined merges stage or fewer than the
-// compute units, within one workgroup's LDS.
+// compute units, within one workgroup's registers and LDS.
 bool merge_cases_direct_applies(int dtype, bool pay, uint32_t cap, int64_t P);
 
 // Steps 3-4 and the merges in one launch, one kWideMergeThreads workgroup per
-// subproblem (each computes its own descriptor from xbar / ybar).
+// subproblem: each computes its own descriptor from xbar / ybar, stages its
+// inputs in LDS and writes its merged outputs straight to memory.
 hipError_t launch_merge_cases_direct(int dtype, const void* keys, const uint32_t* pay, int64_t n,
                                      int64_t m, int64_t p_a, int64_t p_b, const int64_t* xbar,
                                      const int64_t* ybar, void* out_keys, uint32_t* out_pay,

@@ -555,26 +555,50 @@ __global__ __launch_bounds__(L) void merge_direct_kernel(
     write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
 }
 
+// LDS of merge_cases_direct_kernel: the key and payload windows and the
+// lane-level ranks; the merged outputs go straight to memory.
+template <typename K, bool PAY, int L>
+struct DirectSmem {
+    static __host__ __device__ uint32_t key_bytes(uint32_t cap) {
+        return MergeSmem<K, PAY, L>::key_slots(cap) * (uint32_t)sizeof(K);
+    }
+    static __host__ __device__ uint32_t pay_bytes(uint32_t cap) {
+        return PAY ? MergeSmem<K, PAY, L>::pay_slots(cap) * 4u : 0u;
+    }
+    static __host__ __device__ uint32_t bytes(uint32_t cap) {
+        return (key_bytes(cap) + pay_bytes(cap) + 2u * (L + 1) * 4u + 15u) & ~15u;
+    }
+};
+
 // Steps 3-4 and the merge of one subproblem per workgroup, for a few large
 // subproblems: the workgroup takes its descriptor from the cross ranks itself
-// (no descriptor pass) and runs L lanes, so that each lane's share stays
-// short and the compute unit holds enough waves to cover the latency of its
-// LDS reads.
-template <typename K, bool PAY, int L>
+// (no descriptor pass), stages the subproblem with all of its 16-byte loads
+// in flight at once (R chunks per thread), and runs L lanes, so that each
+// lane's share stays short and the compute unit holds enough waves to cover
+// the latency of its LDS reads.  The lanes write their merged pieces to
+// memory themselves, which leaves LDS to the inputs: two such workgroups
+// share a compute unit where one with output buffers would fit.
+template <typename K, bool PAY, int L, int R>
 __global__ __launch_bounds__(L) void merge_cases_direct_kernel(
     const K* __restrict__ keys, const uint32_t* __restrict__ pay, RcpBlocks BA, RcpBlocks BB,
     const int64_t* __restrict__ xbar, const int64_t* __restrict__ ybar, K* __restrict__ out,
     uint32_t* __restrict__ out_pay, uint32_t cap) {
+    using S = DirectSmem<K, PAY, L>;
     extern __shared__ __align__(16) char smem[];
-    const SmemPtrs<K, PAY, L> sp(smem, cap);
+    K* sKey = reinterpret_cast<K*>(smem);
+    uint32_t* sPay = reinterpret_cast<uint32_t*>(smem + S::key_bytes(cap));
+    int* sXb = reinterpret_cast<int*>(smem + S::key_bytes(cap) + S::pay_bytes(cap));
+    int* sYb = sXb + (L + 1);
     const int64_t nk = BA.len + BB.len;
     const PieceDesc d = case_desc(BA, BB, xbar, ybar, blockIdx.x);
     if (!desc_ok(d, nk, nk, cap) || piece_a(d) + piece_b(d) == 0) return;
     const SegPlan p = make_plan<K, PAY>(d);
-    stage_direct<K, PAY, L>(p, keys, (uint64_t)nk, pay, sp.sKey, sp.sPay);
+    u32x4 rk[R], rp[R];
+    prefetch<K, PAY, L, R>(p, keys, (uint64_t)nk, pay, rk, rp);
+    wait_vm<0>();
+    commit<K, PAY, L, R>(p, rk, rp, sKey, sPay);
     __syncthreads();
-    merge_lanes<K, PAY, L>(p, sp.sKey, sp.sPay, sp.sOut, sp.sIdx, sp.sXb, sp.sYb);
-    write_back<K, PAY, L, 0>(p, sp.sOut, sp.sIdx, out, out_pay);
+    merge_lanes_to_memory<K, PAY, L>(p, sKey, sPay, sXb, sYb, out, out_pay);
 }
 
 // ---------------------------------------------------------------------------
@@ -638,26 +662,56 @@ struct FineSmem {
     }
 };
 
-// 16-byte chunks of src[lo, lo + len) (src 16-byte aligned at index 0) into
-// dst: element lo + k lands at dst[off + k], off = lo % V.
-template <typename E, int L>
-__device__ __forceinline__ int stage_range(const E* src, uint64_t src_len, int64_t lo, int len,
-                                           E* dst) {
+// The A and B input ranges of a small-block workgroup (keys[a_lo, a_lo +
+// na) and keys[b0, b0 + nb), payloads alike) into LDS in 16-byte chunks
+// (src 16-byte aligned at index 0): element lo + k of a range lands at
+// dst[lo % V + k].  fine_load issues up to R chunks per thread of an array,
+// so that every array of the workgroup is in flight before the first LDS
+// store and staging costs one round trip to memory; fine_store writes them
+// and moves chunks past R per thread one by one.
+template <typename E, int L, int R>
+__device__ __forceinline__ void fine_load(const E* src, uint64_t src_len, int64_t a_lo, int na,
+                                          int64_t b0, int nb, u32x4 (&r)[R], int& nA, int& nB) {
     constexpr int V = 16 / sizeof(E);
-    const int off = (int)(lo % V);
-    const int64_t al = lo - off;
-    const __amdgpu_buffer_rsrc_t r = make_rsrc(src + al, (src_len - (uint64_t)al) * sizeof(E));
-    const int nch = (off + len + V - 1) / V;
-    for (int q = threadIdx.x; q < nch; q += L)
-        *reinterpret_cast<u32x4*>(dst + q * V) = buf_load16(r, (uint32_t)q * 16u);
-    return off;
+    const int offA = (int)(a_lo % V), offB = (int)(b0 % V);
+    nA = (offA + na + V - 1) / V;
+    nB = (offB + nb + V - 1) / V;
+    load_windows<L, R>(reinterpret_cast<const char*>(src), src_len * sizeof(E),
+                       (a_lo - offA) * (int64_t)sizeof(E), nA, (b0 - offB) * (int64_t)sizeof(E), nB,
+                       r);
 }
+
+template <typename E, int L, int R>
+__device__ __forceinline__ void fine_store(const E* src, uint64_t src_len, int64_t a_lo, int64_t b0,
+                                           const u32x4 (&r)[R], int nA, int nB, E* dA, E* dB) {
+    constexpr int V = 16 / sizeof(E);
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int q = i * L + t;
+        if (q < nA) *reinterpret_cast<u32x4*>(dA + q * V) = r[i];
+        else if (q < nA + nB) *reinterpret_cast<u32x4*>(dB + (q - nA) * V) = r[i];
+    }
+    if (nA + nB > R * L) {
+        const int64_t alA = a_lo - (int)(a_lo % V), alB = b0 - (int)(b0 % V);
+        const __amdgpu_buffer_rsrc_t rA = make_rsrc(src + alA, (src_len - (uint64_t)alA) * sizeof(E));
+        const __amdgpu_buffer_rsrc_t rB = make_rsrc(src + alB, (src_len - (uint64_t)alB) * sizeof(E));
+        for (int q = R * L + t; q < nA + nB; q += L) {
+            if (q < nA) *reinterpret_cast<u32x4*>(dA + q * V) = buf_load16(rA, (uint32_t)q * 16u);
+            else *reinterpret_cast<u32x4*>(dB + (q - nA) * V) = buf_load16(rB, (uint32_t)(q - nA) * 16u);
+        }
+    }
+}
+
+// 16-byte chunks per thread of each array that fine_merge_staged_kernel keeps
+// in flight while staging.
+constexpr int kFineChunks = 8;
 
 template <typename K, bool PAY>
 __global__ __launch_bounds__(kFineL) void fine_merge_staged_kernel(
-    const K* __restrict__ keys, const uint32_t* __restrict__ pay, int64_t n, int64_t m,
-    int64_t p_a, int64_t p_b, const int64_t* __restrict__ xbar, const int64_t* __restrict__ ybar,
-    K* __restrict__ out, uint32_t* __restrict__ out_pay, int capA, int capB) {
+    const K* __restrict__ keys, const uint32_t* __restrict__ pay, RcpBlocks BA, RcpBlocks BB,
+    const int64_t* __restrict__ xbar, const int64_t* __restrict__ ybar, K* __restrict__ out,
+    uint32_t* __restrict__ out_pay, int capA, int capB) {
     constexpr int L = kFineL;
     extern __shared__ __align__(16) char smem[];
     const FineSmem fs(capA, capB);
@@ -668,7 +722,7 @@ __global__ __launch_bounds__(kFineL) void fine_merge_staged_kernel(
     uint32_t* qB = qA + fs.ka;
     uint32_t* qC = qB + fs.kb;
 
-    const Blocks<int64_t> BA(n, p_a), BB(m, p_b);
+    const int64_t n = BA.len, m = BB.len, p_a = BA.p, p_b = BB.p;
     const int64_t i0 = (int64_t)blockIdx.x * kFineG;
     if (i0 >= p_a) return;
     const int64_t i1 = i0 + kFineG < p_a ? i0 + kFineG : p_a;
@@ -705,21 +759,32 @@ __global__ __launch_bounds__(kFineL) void fine_merge_staged_kernel(
         return;
     }
 
+    // this thread's first piece: its cross-rank reads go out before the
+    // staging loads
+    const bool has0 = threadIdx.x < npieces;
+    Piece<int64_t> pc0;
+    pc0.a_lo = pc0.a_hi = a_lo;
+    pc0.b_lo = pc0.b_hi = b_lo;
+    pc0.c_off = c_lo;
+    if (has0) pc0 = piece(threadIdx.x);
+
     const uint64_t total = (uint64_t)(n + m);
-    const int offA = stage_range<K, L>(keys, total, a_lo, (int)na, sA);
-    const int offB = stage_range<K, L>(keys, total, n + b_lo, (int)nb, sB);
-    if (PAY) {
-        stage_range<uint32_t, L>(pay, total, a_lo, (int)na, qA);
-        stage_range<uint32_t, L>(pay, total, n + b_lo, (int)nb, qB);
-    }
+    constexpr int RC = kFineChunks;
+    u32x4 rk[RC], rp[RC];
+    int nkA, nkB, npA = 0, npB = 0;
+    fine_load<K, L, RC>(keys, total, a_lo, (int)na, n + b_lo, (int)nb, rk, nkA, nkB);
+    if (PAY) fine_load<uint32_t, L, RC>(pay, total, a_lo, (int)na, n + b_lo, (int)nb, rp, npA, npB);
+    fine_store<K, L, RC>(keys, total, a_lo, n + b_lo, rk, nkA, nkB, sA, sB);
+    if (PAY) fine_store<uint32_t, L, RC>(pay, total, a_lo, n + b_lo, rp, npA, npB, qA, qB);
     constexpr int V = 16 / sizeof(K);
+    const int offA = (int)(a_lo % V), offB = (int)((n + b_lo) % V);
     const int offC = (int)(c_lo % V);
     const int offCP = (int)(c_lo % 4);
     const int offPA = (int)(a_lo % 4), offPB = (int)((n + b_lo) % 4);
     __syncthreads();
 
     for (int64_t idx = threadIdx.x; idx < npieces; idx += L) {
-        const Piece<int64_t> pc = piece(idx);
+        const Piece<int64_t> pc = idx == threadIdx.x ? pc0 : piece(idx);
         if (!inside(pc)) continue;  // cannot happen for cross ranks of sorted inputs
         const int la = (int)(pc.a_hi - pc.a_lo), lb = (int)(pc.b_hi - pc.b_lo);
         const int ia = offA + (int)(pc.a_lo - a_lo), ib = offB + (int)(pc.b_lo - b_lo);
@@ -872,10 +937,10 @@ static int resident_per_cu(Kern kern, uint32_t lds, std::atomic<uint64_t>& last)
 // Largest subproblem the register-pipelined kernel with R chunks per thread
 // can stage: key chunks <= cap / V + 4 and payload chunks <= cap / 4 + 4 must
 // not exceed R * L.
-template <typename K, bool PAY>
+template <typename K, bool PAY, int L = kMergeThreads>
 static bool fits_regs(uint32_t cap, int R) {
     constexpr int V = Vec<K>::N;
-    const int64_t slots = (int64_t)R * kMergeThreads;
+    const int64_t slots = (int64_t)R * L;
     if ((int64_t)cap / V + 5 > slots) return false;
     if (PAY && (int64_t)cap / 4 + 4 > slots) return false;
     return true;
@@ -999,6 +1064,13 @@ uint32_t merge_pack_cap(int dtype, bool pay, uint32_t cap) {
     return best;
 }
 
+// Register chunks per thread for merge_cases_direct_kernel (0: none fits).
+template <typename K, bool PAY>
+static int direct_regs(uint32_t cap) {
+    if (fits_regs<K, PAY, kWideMergeThreads>(cap, 2)) return 2;
+    return fits_regs<K, PAY, kWideMergeThreads>(cap, 5) ? 5 : 0;
+}
+
 bool merge_cases_direct_applies(int dtype, bool pay, uint32_t cap, int64_t P) {
     if (P <= 0 || P > (int64_t)kWideMergeMaxWgPerCu * device_cu_count()) return false;
     bool ok = false;
@@ -1007,11 +1079,12 @@ bool merge_cases_direct_applies(int dtype, bool pay, uint32_t cap, int64_t P) {
         // subproblems past the register-pipelined kernels' reach (one
         // 256-lane workgroup per compute unit there), or fewer subproblems
         // than compute units
-        const bool big = pay ? merge_regs<K, true>(cap) >= 9 || merge_regs<K, true>(cap) == 0
-                             : merge_regs<K, false>(cap) >= 9 || merge_regs<K, false>(cap) == 0;
-        const uint32_t lds = pay ? MergeSmem<K, true, kWideMergeThreads>::bytes(cap)
-                                 : MergeSmem<K, false, kWideMergeThreads>::bytes(cap);
-        ok = (big || P <= device_cu_count()) && lds <= kMaxLds;
+        const int r = pay ? merge_regs<K, true>(cap) : merge_regs<K, false>(cap);
+        const bool big = r >= 9 || r == 0;
+        const bool regs = (pay ? direct_regs<K, true>(cap) : direct_regs<K, false>(cap)) > 0;
+        const uint32_t lds = pay ? DirectSmem<K, true, kWideMergeThreads>::bytes(cap)
+                                 : DirectSmem<K, false, kWideMergeThreads>::bytes(cap);
+        ok = (big || P <= device_cu_count()) && regs && lds <= kMaxLds;
     });
     return ok;
 }
@@ -1023,7 +1096,7 @@ hipError_t launch_merge_cases_direct(int dtype, const void* keys, const uint32_t
     const int64_t P = p_a + p_b;
     if (P <= 0) return hipSuccess;
     constexpr int L = kWideMergeThreads;
-    hipError_t e = hipSuccess;
+    hipError_t e = hipErrorInvalidValue;   // no register layout holds cap
     with_key_type(dtype, [&](auto z) {
         using K = decltype(z);
         auto go = [&](auto kern, std::atomic<bool>& attr, uint32_t lds) {
@@ -1035,11 +1108,17 @@ hipError_t launch_merge_cases_direct(int dtype, const void* keys, const uint32_t
             e = hipGetLastError();
         };
         if (pay) {
-            static std::atomic<bool> attr{false};
-            go(merge_cases_direct_kernel<K, true, L>, attr, MergeSmem<K, true, L>::bytes(cap));
+            const uint32_t lds = DirectSmem<K, true, L>::bytes(cap);
+            const int r = direct_regs<K, true>(cap);
+            static std::atomic<bool> attr2{false}, attr5{false};
+            if (r == 2) go(merge_cases_direct_kernel<K, true, L, 2>, attr2, lds);
+            else if (r == 5) go(merge_cases_direct_kernel<K, true, L, 5>, attr5, lds);
         } else {
-            static std::atomic<bool> attr{false};
-            go(merge_cases_direct_kernel<K, false, L>, attr, MergeSmem<K, false, L>::bytes(cap));
+            const uint32_t lds = DirectSmem<K, false, L>::bytes(cap);
+            const int r = direct_regs<K, false>(cap);
+            static std::atomic<bool> attr2{false}, attr5{false};
+            if (r == 2) go(merge_cases_direct_kernel<K, false, L, 2>, attr2, lds);
+            else if (r == 5) go(merge_cases_direct_kernel<K, false, L, 5>, attr5, lds);
         }
     });
     return e;
@@ -1097,17 +1176,17 @@ hipError_t launch_fine_merge(int dtype, const void* keys, const uint32_t* pay, i
             static std::atomic<bool> attr{false};
             e = allow_big_lds_once(kern, attr);
             if (e == hipSuccess)
-                kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), pay, n, m, p_a, p_b,
-                                                xbar, ybar, static_cast<K*>(out_keys), out_pay,
-                                                capA, capB);
+                kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), pay, RcpBlocks(n, p_a),
+                                                RcpBlocks(m, p_b), xbar, ybar,
+                                                static_cast<K*>(out_keys), out_pay, capA, capB);
         } else {
             auto kern = fine_merge_staged_kernel<K, false>;
             static std::atomic<bool> attr{false};
             e = allow_big_lds_once(kern, attr);
             if (e == hipSuccess)
-                kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), nullptr, n, m, p_a,
-                                                p_b, xbar, ybar, static_cast<K*>(out_keys),
-                                                nullptr, capA, capB);
+                kern<<<grid, kFineL, lds, st>>>(static_cast<const K*>(keys), nullptr,
+                                                RcpBlocks(n, p_a), RcpBlocks(m, p_b), xbar, ybar,
+                                                static_cast<K*>(out_keys), nullptr, capA, capB);
         }
     });
     if (e != hipSuccess) return e;
