@@ -52,4 +52,16 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
                         int64_t count, int64_t tile, char* ws, const BatchLayout& L,
                         hipStream_t st, const LearnedSearch* ls = nullptr);
 
+// partition, cases and merge for jobs whose plan is already in the
+// workspace: subproblem and cross-rank starts at L.off_pstart / L.off_sstart
+// (count + 1 each, exclusive, the last one the total) and the two totals at
+// L.off_totals.  uni_p, uni_s > 0: every job but the last has exactly uni_p
+// subproblems and uni_s cross ranks, so a flat index finds its job by
+// division; 0: by search over the starts.
+hipError_t launch_batch_planned(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
+                                void* out_keys, uint32_t* out_pay, int64_t nout,
+                                const PieceDesc* jobs, int64_t count, int64_t tile, char* ws,
+                                const BatchLayout& L, hipStream_t st, const LearnedSearch* ls,
+                                int64_t uni_p, int64_t uni_s);
+
 }  // namespace sm

@@ -163,6 +163,18 @@ __device__ __forceinline__ int64_t owner(const int64_t* start, int64_t count, in
     return lo;
 }
 
+// Owner of flat index w when every job but the last has `uni` entries (and
+// the last one starts at (count - 1) * uni): a division; otherwise (uni =
+// 0) the search over the starts.
+__device__ __forceinline__ int64_t owner_of(const int64_t* start, int64_t count, int64_t w,
+                                            int64_t uni, double rcp_uni) {
+    if (uni > 0) {
+        const int64_t k = RcpBlocks::div(w, uni, rcp_uni);
+        return k < count - 1 ? k : count - 1;
+    }
+    return owner(start, count, w);
+}
+
 // Rank of x in X[0, len) (rank_high if HIGH) by bounded search from the
 // model's guess; adds the probes to `probes`.
 template <bool HIGH, typename K>
@@ -191,14 +203,15 @@ __global__ __launch_bounds__(256) void batch_partition_kernel(
     const K* __restrict__ keys, const PieceDesc* __restrict__ jobs, int64_t count, int64_t tile,
     uint32_t cap, const int64_t* __restrict__ sstart, const int64_t* __restrict__ totals,
     int64_t s_max, int64_t* __restrict__ ranks, const float* __restrict__ model, float step_frac,
-    unsigned long long* __restrict__ counters) {
+    unsigned long long* __restrict__ counters, int64_t uni_s) {
     // the counts bound S by s_max; the clamp only keeps a corrupted job list
     // inside the workspace
     const int64_t S = min(totals[1], s_max);
+    const double rcp_s = uni_s > 0 ? 1.0 / (double)uni_s : 0.0;
     unsigned long long n_search = 0, n_probe = 0;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S;
          s += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = owner(sstart, count, s);
+        const int64_t k = owner_of(sstart, count, s, uni_s, rcp_s);
         const PieceDesc j = jobs[k];
         int64_t np, ns, p_a, p_b;
         job_counts(j, tile, cap, np, ns, p_a, p_b);
@@ -245,11 +258,12 @@ __global__ __launch_bounds__(256) void batch_cases_kernel(
     const PieceDesc* __restrict__ jobs, int64_t count, int64_t tile, uint32_t cap,
     const int64_t* __restrict__ pstart, const int64_t* __restrict__ sstart,
     const int64_t* __restrict__ totals, const int64_t* __restrict__ ranks, int64_t p_max,
-    PieceDesc* __restrict__ desc) {
+    PieceDesc* __restrict__ desc, int64_t uni_p) {
     const int64_t P = min(totals[0], p_max);
+    const double rcp_p = uni_p > 0 ? 1.0 / (double)uni_p : 0.0;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < P;
          w += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = owner(pstart, count, w);
+        const int64_t k = owner_of(pstart, count, w, uni_p, rcp_p);
         const PieceDesc j = jobs[k];
         int64_t np, ns, p_a, p_b;
         job_counts(j, tile, cap, np, ns, p_a, p_b);
@@ -416,8 +430,6 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
     int64_t* bsum_p = reinterpret_cast<int64_t*>(ws + L.off_bsum_p);
     int64_t* bsum_s = reinterpret_cast<int64_t*>(ws + L.off_bsum_s);
     int64_t* totals = reinterpret_cast<int64_t*>(ws + L.off_totals);
-    int64_t* ranks = reinterpret_cast<int64_t*>(ws + L.off_ranks);
-    PieceDesc* desc = reinterpret_cast<PieceDesc*>(ws + L.off_desc);
 
     plan_scan_kernel<<<(unsigned)L.nblocks, kScanThreads, 0, st>>>(jobs, count, tile, cap, pstart,
                                                                     sstart, bsum_p, bsum_s);
@@ -430,6 +442,24 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
     scan_add_kernel<<<(unsigned)g, 256, 0, st>>>(pstart, sstart, bsum_p, bsum_s, count, totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
+    return launch_batch_planned(dtype, keys, pay, nkeys, out_keys, out_pay, nout, jobs, count, tile,
+                                ws, L, st, ls, 0, 0);
+}
+
+hipError_t launch_batch_planned(int dtype, const void* keys, const uint32_t* pay, int64_t nkeys,
+                                void* out_keys, uint32_t* out_pay, int64_t nout,
+                                const PieceDesc* jobs, int64_t count, int64_t tile, char* ws,
+                                const BatchLayout& L, hipStream_t st, const LearnedSearch* ls,
+                                int64_t uni_p, int64_t uni_s) {
+    if (count <= 0) return hipSuccess;
+    if (ls && (dtype & kDescending)) return hipErrorInvalidValue;  // ascending models only
+    const uint32_t cap = merge_cap_for_tile((int32_t)tile);
+    const int64_t* pstart = reinterpret_cast<const int64_t*>(ws + L.off_pstart);
+    const int64_t* sstart = reinterpret_cast<const int64_t*>(ws + L.off_sstart);
+    const int64_t* totals = reinterpret_cast<const int64_t*>(ws + L.off_totals);
+    int64_t* ranks = reinterpret_cast<int64_t*>(ws + L.off_ranks);
+    PieceDesc* desc = reinterpret_cast<PieceDesc*>(ws + L.off_desc);
+    hipError_t e;
     const int64_t grid = (int64_t)device_cu_count() * 8;
     int64_t gs = (L.s_max + 255) / 256;
     if (gs > grid) gs = grid;
@@ -437,13 +467,13 @@ hipError_t launch_batch(int dtype, const void* keys, const uint32_t* pay, int64_
         using K = decltype(z);
         batch_partition_kernel<K><<<(unsigned)gs, 256, 0, st>>>(
             static_cast<const K*>(keys), jobs, count, tile, cap, sstart, totals, L.s_max, ranks,
-            ls ? ls->model : nullptr, ls ? ls->step_frac : 0.0f, ls ? ls->counters : nullptr);
+            ls ? ls->model : nullptr, ls ? ls->step_frac : 0.0f, ls ? ls->counters : nullptr, uni_s);
     });
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int64_t gp = (L.p_max + 255) / 256;
     if (gp > grid) gp = grid;
     batch_cases_kernel<<<(unsigned)gp, 256, 0, st>>>(jobs, count, tile, cap, pstart, sstart, totals,
-                                                     ranks, L.p_max, desc);
+                                                     ranks, L.p_max, desc, uni_p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_merge_desc(dtype, keys, pay, nkeys, out_keys, out_pay, nout, desc, L.p_max,
                              totals, merge_pack_cap(dtype, pay != nullptr, cap), st, /*packed=*/true);

@@ -262,6 +262,40 @@ __global__ __launch_bounds__(256) void sort_pass_jobs_kernel(int64_t N, int64_t 
 }
 
 
+// Jobs of merge pass w and their plan for the batch engine, when the pairs
+// exceed one merge workgroup: every job but the last is two full runs, so
+// it has uni_p subproblems and uni_s cross ranks, and the engine's
+// exclusive starts are k * uni_p and k * uni_s (the totals, from the host,
+// close the lists).  Replaces the per-job counts and scans of the general
+// engine.
+__global__ __launch_bounds__(256) void sort_pass_plan_kernel(
+    int64_t N, int64_t w, int64_t count, PieceDesc* __restrict__ jobs,
+    int64_t* __restrict__ pstart, int64_t* __restrict__ sstart, int64_t* __restrict__ totals,
+    int64_t uni_p, int64_t uni_s, int64_t P, int64_t S) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= count;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (k == count) {
+            pstart[count] = P;
+            sstart[count] = S;
+            totals[0] = P;
+            totals[1] = S;
+            continue;
+        }
+        const int64_t lo = 2 * k * w;
+        const int64_t mid = lo + w < N ? lo + w : N;
+        const int64_t hi = lo + 2 * w < N ? lo + 2 * w : N;
+        PieceDesc j;
+        j.ka0 = lo;
+        j.kb0 = mid;
+        j.out0 = lo;
+        j.a_f = (uint32_t)(mid - lo);
+        j.b_f = (uint32_t)(hi - mid);
+        jobs[k] = j;
+        pstart[k] = k * uni_p;
+        sstart[k] = k * uni_s;
+    }
+}
+
 // Jobs of merge pass w of the segmented sort: slot t (at width 2w) holds
 // pair k of segment s: [lo, lo + w) with [lo + w, lo + 2w), clipped to the
 // segment, lo = offsets[s] + 2kw; a slot with no pair is an empty job.
@@ -401,22 +435,52 @@ hipError_t launch_sort(int dtype, const void* keys, const uint32_t* pay, int64_t
         // job slots of this pass: one per pair of runs, or (segments) the
         // slot bound at width 2w
         const int64_t count = seg_offsets ? seg_count + N / (2 * w) + 1 : (N + 2 * w - 1) / (2 * w);
-        int64_t g = (count + 255) / 256;
+        int64_t g = (count + 1 + 255) / 256;
         if (g > 4096) g = 4096;
-        if (seg_offsets)
+        const bool whole = !seg_offsets && 2 * w <= (int64_t)cap;
+        const BatchLayout BL = batch_layout(count, N, tile);
+        // subproblems and cross ranks of a job of a + b elements, as the
+        // batch engine counts them
+        auto counts = [&](int64_t a, int64_t b, int64_t& np, int64_t& ns) {
+            if (a + b <= (int64_t)cap) {
+                np = a + b > 0 ? 1 : 0;
+                ns = 0;
+                return;
+            }
+            const int64_t pa = a > 0 ? (a + tile - 1) / tile : 1, pb = b > 0 ? (b + tile - 1) / tile : 1;
+            np = pa + pb;
+            ns = pa + pb + 2;
+        };
+        int64_t uni_p = 0, uni_s = 0;
+        if (seg_offsets) {
             seg_pass_jobs_kernel<<<(unsigned)g, 256, 0, st>>>(seg_offsets, seg_count, w, count, jobs);
-        else
+        } else if (whole) {
             sort_pass_jobs_kernel<<<(unsigned)g, 256, 0, st>>>(N, w, count, jobs);
+        } else {
+            const int64_t lo = 2 * (count - 1) * w;
+            const int64_t mid = lo + w < N ? lo + w : N, hi = lo + 2 * w < N ? lo + 2 * w : N;
+            int64_t np_l, ns_l;
+            counts(w, w, uni_p, uni_s);
+            counts(mid - lo, hi - mid, np_l, ns_l);
+            char* bw = ws + L.off_batch;
+            sort_pass_plan_kernel<<<(unsigned)g, 256, 0, st>>>(
+                N, w, count, jobs, reinterpret_cast<int64_t*>(bw + BL.off_pstart),
+                reinterpret_cast<int64_t*>(bw + BL.off_sstart),
+                reinterpret_cast<int64_t*>(bw + BL.off_totals), uni_p, uni_s,
+                (count - 1) * uni_p + np_l, (count - 1) * uni_s + ns_l);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (!seg_offsets && 2 * w <= (int64_t)cap) {
+        if (whole) {
             // a pair of runs fits one merge workgroup: each job is merged
             // whole, with no cross ranks to find
             e = launch_merge_desc(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, nullptr,
                                   cap, st);
-        } else {
-            const BatchLayout BL = batch_layout(count, N, tile);
+        } else if (seg_offsets) {
             e = launch_batch(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, tile,
                              ws + L.off_batch, BL, st, ls);
+        } else {
+            e = launch_batch_planned(dtype, src_k, src_p, N, dst_k, dst_p, N, jobs, count, tile,
+                                     ws + L.off_batch, BL, st, ls, uni_p, uni_s);
         }
         if (e != hipSuccess) return e;
         char* tk = src_k; src_k = dst_k; dst_k = tk;
