@@ -172,6 +172,39 @@ def test_large_subproblems_few_and_many(dtype, with_pay):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("with_pay", [False, True])
+def test_few_blocks_merge_and_pieces(dtype, with_pay):
+    """Few block starts over large subproblems (group searches, then the
+    workgroups that take their cases from the cross ranks): merge() and
+    partition() + merge_pieces() both give the oracle's bytes, and the
+    partition agrees with the oracle's cross ranks.  Heavy ties, ragged
+    ends, p_a != p_b and an empty side included."""
+    g = np.random.default_rng(120 + DTYPES.index(dtype) + 10 * with_pay)
+    for n, m, p_a, p_b, alpha in [(100_003, 60_001, 40, 25, 50), (30_000, 1, 7, 1, 3),
+                                   (1, 30_000, 1, 9, 3), (0, 20_000, 3, 5, 10),
+                                   (50_000, 50_000, 16, 16, 1), (200_001, 100_000, 100, 60, 1 << 20)]:
+        A, B = rand_sorted(g, n, alpha, dtype), rand_sorted(g, m, alpha, dtype)
+        pa = pb = None
+        if with_pay:
+            pa, pb = datagen.source_tag_payloads(n, m)
+        rk, rp = oracle.merge(A, B, pa, pb)
+        keys = dev(np.concatenate([A, B]))
+        pay = None if pa is None else dev(np.concatenate([pa, pb]).astype(np.uint32))
+        flush(f"few blocks dtype={np.dtype(dtype).name} pay={with_pay} n={n} m={m} "
+              f"p_a={p_a} p_b={p_b}")
+        ck, cp = sm.merge(keys, n, m, pay, p_a=p_a, p_b=p_b)
+        xb, yb = sm.partition(keys, n, m, p_a, p_b)
+        ck2, cp2 = sm.merge_pieces(keys, n, m, p_a, p_b, xb, yb, pay)
+        torch.cuda.synchronize()
+        rx, ry = oracle.cross_ranks(A, B, p_a, p_b)
+        assert np.array_equal(host(xb), rx) and np.array_equal(host(yb), ry)
+        for k, pp in ((ck, cp), (ck2, cp2)):
+            assert np.array_equal(host(k), rk)
+            if with_pay:
+                assert np.array_equal(host(pp), rp)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_forced_few_blocks_large(dtype):
     """Few forced blocks over large arrays: subproblems far beyond one
     workgroup are split again by the method (two levels)."""
