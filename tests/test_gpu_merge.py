@@ -401,3 +401,45 @@ def test_beyond_32bit_indices():
     want = np.concatenate([A[ia], B[jb]])
     got = host(o32[torch.as_tensor(pos, device=dev_)]).view(np.uint32)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.slow
+def test_payloads_beyond_4gib():
+    """n = m = 2^30 uint32 keys with uint32 payloads (each array 4 GiB, so
+    neither keys nor payloads fit one 32-bit buffer resource): the output
+    keys are non-decreasing, and for sampled elements of A and of B the
+    slot the oracle's cross rank gives holds that key and its payload (the
+    element's index in A||B), which a stable merge fixes exactly."""
+    n = m = 1 << 30
+    dev_ = torch.device("cuda:0")
+    gen = torch.Generator(device=dev_)
+    gen.manual_seed(datagen.BASE_SEED + 10)
+    flush("2^30 + 2^30 with payloads: generate")
+    keys = torch.empty(n + m, dtype=torch.int32, device=dev_)
+    for lo in (0, n):
+        steps = torch.randint(0, 2, (n,), generator=gen, device=dev_, dtype=torch.int32)
+        keys[lo:lo + n] = torch.cumsum(steps, 0, dtype=torch.int32)
+        del steps
+    keys = keys.view(torch.uint32)
+    pay = torch.arange(n + m, dtype=torch.int64, device=dev_).to(torch.int32).view(torch.uint32)
+    flush("2^30 + 2^30 with payloads: gpu merge")
+    out, out_pay = sm.merge(keys, n, m, pay)
+    torch.cuda.synchronize()
+    del pay
+    o32 = out.view(torch.int32)
+    for lo in range(0, n + m, 1 << 29):
+        hi = min(lo + (1 << 29) + 1, n + m)
+        assert bool((o32[lo + 1:hi] >= o32[lo:hi - 1]).all()), f"not sorted near {lo}"
+    flush("2^30 + 2^30 with payloads: sampled ranks")
+    A = host(keys[:n])
+    B = host(keys[n:])
+    g = np.random.default_rng(4)
+    ia = g.integers(0, n, 3000)
+    jb = g.integers(0, m, 3000)
+    pos = np.concatenate([ia + np.array([oracle.rank_low(A[i], B) for i in ia]),
+                          jb + np.array([oracle.rank_high(B[j], A) for j in jb])])
+    idx = torch.as_tensor(pos, device=dev_)
+    got_k = host(o32[idx]).view(np.uint32)
+    got_p = host(out_pay.view(torch.int32)[idx]).view(np.uint32)
+    assert np.array_equal(got_k, np.concatenate([A[ia], B[jb]]))
+    assert np.array_equal(got_p, np.concatenate([ia, n + jb]).astype(np.uint32))
