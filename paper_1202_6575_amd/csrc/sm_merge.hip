@@ -637,14 +637,31 @@ __device__ __forceinline__ void fine_piece_global(const K* __restrict__ keys,
         ia += !tb;
         ++o;
     }
-    for (; ia < pc.a_hi; ++ia, ++o) {
-        out[o] = A[ia];
-        if (PAY) out_pay[o] = pay[ia];
-    }
-    for (; ib < pc.b_hi; ++ib, ++o) {
-        out[o] = B[ib];
-        if (PAY) out_pay[o] = pay[n + ib];
-    }
+    // the rest of one part is a copy: eight loads in flight before the
+    // stores (under heavy duplicates most pieces here are copies of a B
+    // block)
+    auto copy = [&](const K* src, const uint32_t* psrc, int64_t i, int64_t end) {
+        for (; i + 8 <= end; i += 8, o += 8) {
+            K v[8];
+            uint32_t q[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                v[e] = src[i + e];
+                if (PAY) q[e] = psrc[i + e];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                out[o + e] = v[e];
+                if (PAY) out_pay[o + e] = q[e];
+            }
+        }
+        for (; i < end; ++i, ++o) {
+            out[o] = src[i];
+            if (PAY) out_pay[o] = psrc[i];
+        }
+    };
+    copy(A, pay, ia, pc.a_hi);
+    copy(B, PAY ? pay + n : nullptr, ib, pc.b_hi);
 }
 
 // LDS of the staged small-block merge: A window, B window, output window
