@@ -235,8 +235,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
                                              0x00020000);
 }
 
+// Non-temporal (cache policy bit 1, "nt" on gfx950): every caller streams
+// data it reads once (staging windows, descriptors), and keeping those lines
+// out of the caches' reuse order leaves room for what is read again, such
+// as the upper levels of the cross-rank searches.
 __device__ __forceinline__ u32x4 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
-    return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 2);
 }
 
 // ---------------------------------------------------------------------------
