@@ -966,8 +966,12 @@ __device__ __forceinline__ void write_out(const E* sArr, int off, int s, E* base
     constexpr int V = 16 / sizeof(E);
     const int t = threadIdx.x;
     const int q0 = (off + V - 1) / V, q1 = (off + s) / V;   // full chunks [q0, q1)
+    // the merged stream is written once and not read back soon:
+    // non-temporal stores keep it from evicting the cached lines that the
+    // cross-rank searches reuse
     auto chunk = [&](int q) {
-        *reinterpret_cast<u32x4*>(base_out + q * V) = *reinterpret_cast<const u32x4*>(sArr + q * V);
+        __builtin_nontemporal_store(*reinterpret_cast<const u32x4*>(sArr + q * V),
+                                    reinterpret_cast<u32x4*>(base_out + q * V));
     };
     if (RW > 0) {
         // all LDS reads first (a chunk past the end re-reads chunk q0 and is
@@ -981,9 +985,6 @@ __device__ __forceinline__ void write_out(const E* sArr, int off, int s, E* base
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int q = q0 + r * L + t;
-            // the merged stream is written once and not read back soon:
-            // non-temporal stores keep it from evicting the cached lines
-            // that the cross-rank searches reuse
             if (q < q1) __builtin_nontemporal_store(v[r], reinterpret_cast<u32x4*>(base_out + q * V));
         }
     } else {
