@@ -145,7 +145,6 @@ template <typename K, bool PAY, int RUN>
 __global__ __launch_bounds__(run_threads<RUN>()) void sort_runs_kernel(
     const K* keys, const uint32_t* pay, int64_t N, K* out, uint32_t* out_pay,
     const int64_t* __restrict__ seg_offsets, int64_t seg_count) {
-    constexpr int T = run_threads<RUN>();
     static_assert(RUN % 16 == 0 && (RUN & (RUN - 1)) == 0, "RUN: a power of two");
     __shared__ __align__(16) RunSmem<K, PAY, RUN> s;
     const int t = threadIdx.x;
