@@ -68,12 +68,14 @@ bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Block length in elements when none is given: a subproblem then holds up to
-// twice this, and one merge workgroup stages it in LDS.  Each is the largest
-// length (measured on MI355X) at which four merge workgroups still share a
-// compute unit's 160 KiB of LDS.
+// twice this, and one merge workgroup stages it in LDS.  Keys only, and 64-bit
+// keys with payloads: the largest length (measured on MI355X) at which four
+// merge workgroups still share a compute unit's 160 KiB of LDS.  32-bit keys
+// with payloads: 1408, three workgroups per compute unit, which measured
+// faster than 1152 (four per unit) in merges and in the sort's passes.
 int32_t default_tile(int dtype, bool pay) {
     if (key_bytes(dtype) == 8) return pay ? 1024 : 1152;
-    return pay ? 1152 : 2368;
+    return pay ? 1408 : 2368;
 }
 
 int32_t pick_tile(int dtype, bool pay, const sm_options* opt) {
